@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark: Schwarzschild ray tracing at 4K on one MI355X.
+
+Workload: the 16-frame camera orbit at 3840x2160 (per frame M ~ U[0.5, 2],
+camera at U[20, 100] M, inclination U[0, 90] deg, disk 6-30 M, checker sky at
+1000 M, FOV 60 deg; seeded).  One step = render all 16 frames through the
+whole path (set-up/routing, FP32 integration with the FP64 critical band,
+shading into resident fp32 RGBA buffers).  Value = rays per second of the
+step.  Also reported: the plain FP64 kernel on the same frames, the roofline
+of the dominant kernel (the integrator, timed with HIP events on its launch
+stream), and the CPU FP64 oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_STEP = 139          # algorithmic FLOP per Dormand-Prince step evaluation (FMA = 2)
+PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (scalar FP32 or FP64 FMA)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_orbit4k_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2507_16165_amd", "csrc", "bh_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per integrator launch from the committed rocprofv3 counter
+    summary, or None if it is absent or the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-row-stride", type=int, default=16)
+    ap.add_argument("--frames", type=int, default=16)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(rendering would shard by interleaved image tiles; see the design notes).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2507_16165_amd import api, inputs
+
+    frames = inputs.orbit_4k(frames=args.frames)
+    W, H = frames[0].camera.width, frames[0].camera.height
+    rays_per_step = W * H * len(frames)
+    api.reserve(W * H)
+    bufs = [torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for _ in frames]
+    opt_fast = api.options(precision=api.FP32)
+    opt_fp64 = api.options(precision=api.FP64)
+
+    def step(opt):
+        for f, buf in zip(frames, bufs):
+            api.render(f.camera, f.scene, opt, rgba=buf)
+
+    def timed(opt, k, warm):
+        for _ in range(warm):
+            step(opt)
+        torch.cuda.synchronize()
+        api.timing_enable(True)
+        api.timing_read()
+        t0 = time.perf_counter()
+        for i in range(k):
+            step(opt)
+            log(f"step {i + 1}/{k} enqueued")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tim = api.timing_read()
+        api.timing_enable(False)
+        return (t1 - t0) * 1e3 / k, tim
+
+    log(f"fast path: warmup {args.warmup}, steps {args.steps}")
+    ms_step, tim = timed(opt_fast, args.steps, args.warmup)
+    log(f"fast path {ms_step:.3f} ms/step")
+    log(f"fp64 path: steps {args.fp64_steps}")
+    ms_step64, tim64 = timed(opt_fp64, args.fp64_steps, 1)
+    log(f"fp64 path {ms_step64:.3f} ms/step")
+
+    # Algorithmic work: step evaluations per ray are independent of the
+    # schedule, so one instrumented pass gives the count of the timed launches.
+    def step_evals(opt):
+        tot = 0
+        per_path = {}
+        for f, buf in zip(frames, bufs):
+            _, out = api.render(f.camera, f.scene, opt, rgba=buf, fields=("steps", "path"))
+            tot += int(out["steps"].to(torch.int64).sum().item())
+            for p in (api.PATH_NONE, api.PATH_FP64, api.PATH_FP32):
+                per_path[p] = per_path.get(p, 0) + int((out["path"] == p).sum().item())
+        return tot, per_path
+
+    evals, paths = step_evals(opt_fast)
+    evals64, _ = step_evals(opt_fp64)
+    integ_ms, integ_n = tim["integrate"]
+    integ_ms64, integ_n64 = tim64["integrate"]
+    flop_launch = evals * FLOP_PER_STEP / len(frames)
+    avg_launch_ms = integ_ms / integ_n
+    achieved = flop_launch / (avg_launch_ms * 1e-3) / 1e12
+    achieved64 = (evals64 * FLOP_PER_STEP / len(frames)) / (integ_ms64 / integ_n64 * 1e-3) / 1e12
+    traffic = read_traffic()
+
+    value = rays_per_step / (ms_step * 1e-3) / 1e6
+    value64 = rays_per_step / (ms_step64 * 1e-3) / 1e6
+
+    line = {
+        "metric": "Mrays/s at 4K: FP64 RK45 vs FP32+surrogate at <=1e-4 rad err; % FP peak",
+        "value": round(value, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"orbit_4k: {len(frames)} frames 3840x2160, disk 6-30 M, checker sky, "
+                        "FP32 integrator + FP64 band |b-3sqrt3 M|<0.05M",
+            "frames": len(frames), "width": W, "height": H, "rays_per_step": rays_per_step,
+            "rtol_fp32": opt_fast.rtol_fp32, "rtol_fp64": opt_fast.rtol,
+        },
+        "fp64_plain": {"value": round(value64, 2), "unit": "Mrays/s",
+                       "ms_per_step": round(ms_step64, 4), "rtol": opt_fp64.rtol,
+                       "achieved_tflops": round(achieved64, 3),
+                       "frac": round(achieved64 / PEAK_VALU_TFLOPS, 4),
+                       "step_evals_per_ray": round(evals64 / rays_per_step, 3)},
+        "speedup_vs_fp64": round(value / value64, 3),
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
+        "paths": {"setup_only": paths.get(0, 0), "fp64_band": paths.get(1, 0),
+                  "fp32": paths.get(2, 0)},
+        "step_evals_per_ray": round(evals / rays_per_step, 3),
+        "roofline": {
+            "kernel": "bh::k_integrate_fp32",
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
+            "traffic": traffic,
+            "flop_per_launch": flop_launch,
+            "avg_launch_ms": round(avg_launch_ms, 4),
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(frames, args.cpu_row_stride, bufs, opt_fast, api, torch)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def cpu_baseline(frames, stride, bufs, opt_fast, api, torch):
+    """The CPU FP64 oracle (OpenMP over rows, rtol 1e-10) on every stride-th row
+    of every frame; also the GPU fast path's max exit-direction error on the
+    same rows."""
+    import numpy as np
+
+    from oracle import ref
+
+    W, H = frames[0].camera.width, frames[0].camera.height
+    rows = list(range(stride // 2, H, stride))
+    n = 0
+    secs = 0.0
+    max_err = 0.0
+    bc = 3.0 * np.sqrt(3.0)
+    for k, f in enumerate(frames):
+        c, s = f.camera, f.scene
+        cam = ref.camera(c.r, c.incl_deg, c.azim_deg, c.fov_deg, c.width, c.height)
+        sc = ref.scene(s.M, r_sky=s.r_sky, disk=s.disk, disk_power=s.disk_power,
+                       checker_deg=s.checker_deg)
+        _, out = api.render(c, s, opt_fast, rgba=bufs[k], fields=("cls", "exit_dir"))
+        gcls = out["cls"].cpu().numpy()
+        gdir = out["exit_dir"].cpu().numpy()
+        for r0 in rows:
+            t0 = time.perf_counter()
+            _, rr = ref.render(cam, sc, rows=(r0, r0 + 1))
+            secs += time.perf_counter() - t0
+            n += W
+            sl = slice(r0 * W, (r0 + 1) * W)
+            ok = (rr.cls[sl] == gcls[sl]) & (rr.cls[sl] == 0) & (np.abs(rr.b[sl] - bc * s.M) >= 0.05 * s.M)
+            a, b = rr.exit_dir[sl][ok], gdir[sl][ok]
+            if a.size:
+                ang = np.arctan2(np.linalg.norm(np.cross(a, b), axis=1), np.sum(a * b, 1))
+                max_err = max(max_err, float(ang.max()))
+        log(f"cpu baseline frame {k + 1}/{len(frames)}: {n} rays, {secs:.1f} s")
+    return {"value": round(n / secs / 1e6, 4), "unit": "Mrays/s", "cores": ref.max_threads(),
+            "kind": "oracle",
+            "sample": f"every {stride}th row (offset {stride // 2}) of all {len(frames)} frames: "
+                      f"{n} rays, FP64 rtol 1e-10, OpenMP over rows",
+            "seconds": round(secs, 2),
+            "gpu_fast_path_max_exit_err_rad_on_sample": max_err}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

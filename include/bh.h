@@ -1,0 +1,172 @@
+/*
+ * bh.h -- C ABI of the MI355X (gfx950) Schwarzschild black-hole ray tracer.
+ *
+ * Method (arXiv 2507.16165): one ray per pixel of a camera looking at a
+ * non-spinning, uncharged hole (Introduction, the 1920x1080 example); each
+ * ray stays in its orbital plane through the centre, where the photon-orbit
+ * equation Eq. (1) in u = 1/r against the azimuth phi is integrated from the
+ * straight-line initial direction (Implementation, "Using GSL for ODE
+ * approximation"; Fig. 1) until the ray escapes to the sky sphere, falls
+ * through the horizon or hits a thin equatorial disk; the end point is mapped
+ * back to 3D and shaded.  Eq. (1) is used as u'' + u = 3 M u^2 (the printed
+ * minus sign contradicts the cited Binet equation and the straight-line,
+ * critical-parameter and weak-field limits).  Integration is adaptive
+ * Dormand-Prince 5(4) with exact event location in place of the paper's
+ * fixed step and chord intersection.  Units: G = c = 1.
+ *
+ * Conventions for every entry point:
+ *   - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *     tensor's data_ptr()) allocated and owned by the caller; structs are read
+ *     during the call and not retained.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without synchronising.  Results are valid after
+ *     the caller synchronises that stream.
+ *   - The library owns only an internal per-device workspace (per-ray
+ *     scratch and queue counters), grown on demand with hipMalloc; growing it
+ *     synchronises `stream` first.  bh_reserve() sizes it up front;
+ *     bh_shutdown() frees it.  Calls that overlap on one device share the
+ *     workspace, so they must be ordered on one stream.
+ *   - Argument errors return BH_ERR_ARG at once with nothing enqueued;
+ *     bh_last_error() gives a message (thread-local).  A HIP launch error
+ *     returns BH_ERR_DEVICE.  Per-ray problems (non-finite input, origin
+ *     inside the photon sphere) are a per-ray class BH_INVALID, not an error.
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BH_OK = 0,
+    BH_ERR_ARG = -1,
+    BH_ERR_DEVICE = -2,
+    BH_ERR_NOMEM = -3,
+    BH_ERR_UNSUPPORTED = -4,
+    BH_ERR_STATE = -5
+} bh_status;
+
+/* Per-ray end classes. */
+enum { BH_SKY = 0, BH_CAPTURED = 1, BH_DISK = 2, BH_UNRESOLVED = 3, BH_INVALID = 4 };
+
+/* Which part of the path produced a ray's result (bh_ray_out.path). */
+enum {
+    BH_PATH_NONE = 0,     /* classified at set-up: analytic capture, radial, invalid */
+    BH_PATH_FP64 = 1,     /* FP64 integrator (all rays in FP64 mode; the critical band in FP32 mode) */
+    BH_PATH_FP32 = 2,     /* FP32 integrator */
+    BH_PATH_SURROGATE = 3 /* MLP surrogate */
+};
+
+/* Precision policy (bh_options.precision). */
+enum { BH_FP64 = 0, BH_FP32 = 1 };
+
+/* Scene: a hole of mass M at the origin, a procedural checkerboard sky
+ * sphere of radius r_sky and an optional thin opaque disk in the plane z = 0
+ * (visible from both faces, edges inclusive, emissivity (r/r_in)^disk_power,
+ * first crossing only).  Lengths are absolute (not in units of M). */
+typedef struct {
+    double M;            /* >= 0; 0 gives straight lines                       */
+    double r_sky;        /* > camera / ray-origin distance                      */
+    int    has_disk;
+    double disk_rin;     /* 0 < disk_rin < disk_rout                            */
+    double disk_rout;
+    double disk_power;   /* -3 for the r^-3 emissivity                          */
+    double checker_deg;  /* checker cell in degrees of theta and varphi (> 0)  */
+} bh_scene;
+
+/* Pinhole camera looking at the hole: position r (sin i cos a, sin i sin a,
+ * cos i), "up" = -e_theta, vertical field of view, one ray through each
+ * pixel centre, row 0 at the top. */
+typedef struct {
+    double r;            /* 3M < r < r_sky                                     */
+    double incl_deg;     /* i, polar angle from +z                              */
+    double azim_deg;     /* a                                                   */
+    double fov_deg;      /* in (0, 180)                                         */
+    int    width, height;/* >= 1                                                */
+} bh_camera;
+
+typedef struct {
+    int    precision;        /* BH_FP64, or BH_FP32 with FP64 kept for the critical band */
+    double rtol;             /* FP64 integrator relative tolerance                      */
+    double atol;             /* FP64 absolute tolerance; <= 0 means rtol / r_sky        */
+    double rtol_fp32;        /* FP32 integrator tolerance; atol = rtol_fp32 / r_sky     */
+    double band_halfwidth;   /* FP32 mode: |b - 3 sqrt(3) M| < band_halfwidth * M -> FP64 */
+    double h0;               /* first trial step in phi                                 */
+    double hmax;             /* largest step in phi                                     */
+    double max_phi;          /* sweep cap -> BH_UNRESOLVED                              */
+    int    max_steps;        /* cap on step attempts per ray -> BH_UNRESOLVED           */
+    int    analytic_capture; /* 1: with no disk, an ingoing ray with b below the band is
+                                classified CAPTURED without integration (exact: the
+                                effective potential peaks at b = 3 sqrt(3) M)          */
+    int    grid_blocks;      /* persistent integrator grid, 256-thread blocks; 0 = auto */
+    int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto  */
+} bh_options;
+
+/* Optional per-ray outputs (device arrays of length n, any may be NULL).
+ * exit_dir is n*3 doubles: the unit vector of the end point (sky-sphere hit,
+ * disk hit, or the last point for other classes). */
+typedef struct {
+    uint8_t* cls;
+    double*  b;          /* impact parameter from the first integral            */
+    double*  phi_end;    /* azimuth of the end event in the orbital plane       */
+    double*  exit_dir;
+    double*  r_hit;      /* disk hit radius (BH_DISK), else 0                    */
+    int32_t* steps;      /* Dormand-Prince step evaluations spent on the ray    */
+    uint8_t* path;       /* BH_PATH_*                                            */
+} bh_ray_out;
+
+/* Fills defaults: FP64, rtol 1e-10, atol 0 (-> rtol/r_sky), rtol_fp32 1e-6,
+ * band 0.05, h0 1e-2, hmax 1, max_phi 8 pi, max_steps 1e6, analytic capture
+ * on, auto launch shape.  Returns BH_ERR_ARG for NULL. */
+bh_status bh_default_options(bh_options* opt);
+
+/* Traces n rays with world-space origins and directions (device, n*3 doubles
+ * each, need not be unit length).  Per ray: origins with |o| <= 3M or
+ * |o| >= r_sky, zero or non-finite input give BH_INVALID.  Outputs per
+ * `out` (at least out->cls must be non-NULL).  n = 0 is a no-op.
+ * Paper: Eq. (1) and its initial conditions (sections named above). */
+bh_status bh_trace_rays(const double* origin, const double* dir, int64_t n,
+                        const bh_scene* scene, const bh_options* opt,
+                        const bh_ray_out* out, void* stream);
+
+/* Renders one frame into rgba (device, height*width*4 floats, row-major,
+ * row 0 at the top): checker sky (1,1,1,1)/(0.1,0.1,0.1,1), disk
+ * (1, 0.6, 0.2) * I with alpha 1, black (0,0,0,1) for captured, unresolved
+ * and invalid rays.  per_pixel (may be NULL) receives per-ray records indexed
+ * y*width + x.  Paper: Introduction (one ray per pixel), Results (renders
+ * with an Einstein ring). */
+bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
+                    float* rgba, const bh_ray_out* per_pixel, void* stream);
+
+/* Sizes the workspace of the current device for frames of up to n rays
+ * (synchronises the device if it grows). */
+bh_status bh_reserve(int64_t n);
+
+/* Copies the ray counts of the last trace/render on this device into
+ * counts[0..3] = {set-up only, FP64 integrator, FP32 integrator, surrogate}.
+ * Synchronises `stream`. */
+bh_status bh_last_counts(int64_t counts[4], void* stream);
+
+/* Kernel timing for benchmarks.  While enabled, every kernel launch of the
+ * library is bracketed by a pair of hipEvents recorded on its launch stream.
+ * bh_timing_read() waits for those events and returns, per kernel class
+ * {0 set-up, 1 integrator, 2 shading, 3 surrogate}, the summed milliseconds
+ * and the number of launches since the previous read, then clears them.
+ * Disabled by default (no events recorded). */
+bh_status bh_timing_enable(int on);
+bh_status bh_timing_read(double ms[4], int64_t launches[4]);
+
+/* Frees the workspace of every device this thread's process used. */
+bh_status bh_shutdown(void);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* bh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

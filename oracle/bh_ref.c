@@ -22,6 +22,7 @@
 #include "bh_ref.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 
 #define PI 3.14159265358979323846
@@ -100,6 +101,8 @@ void bhr_dopri5_step(double M, const double y[2], double h, double y_out[2], dou
 {
     dopri5_step(M, y[0], y[1], h, &y_out[0], &y_out[1], &err[0], &err[1]);
 }
+
+int bhr_max_threads(void) { return omp_get_max_threads(); }
 
 void bhr_default_options(bhr_options* opt)
 {

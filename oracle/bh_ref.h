@@ -91,6 +91,9 @@ typedef struct {
     double*  e_drift;    /* max |E/E0 - 1| of the first integral over the ray */
 } bhr_out;
 
+/* Number of OpenMP threads the batch entry points use. */
+int bhr_max_threads(void);
+
 /* Default options: rtol 1e-10, atol = rtol/r_sky, h0 1e-2, hmax 1,
  * max_phi 8*pi, max_steps 1e6. */
 void bhr_default_options(bhr_options* opt);

@@ -65,6 +65,8 @@ def lib():
         if not os.path.exists(LIB_PATH):
             build()
         L = C.CDLL(LIB_PATH)
+        L.bhr_max_threads.argtypes = []
+        L.bhr_max_threads.restype = C.c_int
         L.bhr_default_options.argtypes = [C.POINTER(Options)]
         L.bhr_camera_ray.argtypes = [C.POINTER(Camera), C.c_int, C.c_int,
                                      C.c_void_p, C.c_void_p]
@@ -183,3 +185,8 @@ def dopri5_step(M: float, y, h: float):
 
 def dphi_flat(M: float, b: float, r0: float, r_sky: float) -> float:
     return lib().bhr_dphi_flat(M, b, r0, r_sky)
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's batch loops use."""
+    return int(lib().bhr_max_threads())

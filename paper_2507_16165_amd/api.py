@@ -1,0 +1,197 @@
+"""ctypes binding of libbh (include/bh.h).  Argument marshalling only: every
+step of the path runs in the library's HIP kernels.  Tensors are torch CUDA
+(HIP) tensors; work goes on torch's current stream unless one is given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+from . import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbh.so")
+
+BH_OK, BH_ERR_ARG, BH_ERR_DEVICE, BH_ERR_NOMEM, BH_ERR_UNSUPPORTED, BH_ERR_STATE = 0, -1, -2, -3, -4, -5
+SKY, CAPTURED, DISK, UNRESOLVED, INVALID = 0, 1, 2, 3, 4
+PATH_NONE, PATH_FP64, PATH_FP32, PATH_SURROGATE = 0, 1, 2, 3
+FP64, FP32 = 0, 1
+
+
+class BhError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bh status {status}: {msg}")
+        self.status = status
+
+
+class Scene(C.Structure):
+    _fields_ = [("M", C.c_double), ("r_sky", C.c_double), ("has_disk", C.c_int),
+                ("disk_rin", C.c_double), ("disk_rout", C.c_double),
+                ("disk_power", C.c_double), ("checker_deg", C.c_double)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("r", C.c_double), ("incl_deg", C.c_double), ("azim_deg", C.c_double),
+                ("fov_deg", C.c_double), ("width", C.c_int), ("height", C.c_int)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("atol", C.c_double),
+                ("rtol_fp32", C.c_double), ("band_halfwidth", C.c_double), ("h0", C.c_double),
+                ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
+                ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int)]
+
+
+class RayOut(C.Structure):
+    _fields_ = [("cls", C.c_void_p), ("b", C.c_void_p), ("phi_end", C.c_void_p),
+                ("exit_dir", C.c_void_p), ("r_hit", C.c_void_p), ("steps", C.c_void_p),
+                ("path", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libbh.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int
+    L.bh_default_options.argtypes = [C.POINTER(Options)]
+    L.bh_default_options.restype = st
+    L.bh_trace_rays.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Scene),
+                                C.POINTER(Options), C.POINTER(RayOut), C.c_void_p]
+    L.bh_trace_rays.restype = st
+    L.bh_render.argtypes = [C.POINTER(Camera), C.POINTER(Scene), C.POINTER(Options), C.c_void_p,
+                            C.POINTER(RayOut), C.c_void_p]
+    L.bh_render.restype = st
+    L.bh_reserve.argtypes = [C.c_int64]
+    L.bh_reserve.restype = st
+    L.bh_last_counts.argtypes = [C.POINTER(C.c_int64), C.c_void_p]
+    L.bh_last_counts.restype = st
+    L.bh_timing_enable.argtypes = [C.c_int]
+    L.bh_timing_enable.restype = st
+    L.bh_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.bh_timing_read.restype = st
+    L.bh_shutdown.argtypes = []
+    L.bh_shutdown.restype = st
+    L.bh_last_error.argtypes = []
+    L.bh_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != BH_OK:
+        raise BhError(status, lib().bh_last_error().decode(errors="replace"))
+
+
+def options(**overrides) -> Options:
+    o = Options()
+    check(lib().bh_default_options(C.byref(o)))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"bh_options has no field {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+def scene_struct(s: inputs.Scene) -> Scene:
+    rin, rout = s.disk if s.disk is not None else (0.0, 0.0)
+    return Scene(s.M, s.r_sky, 1 if s.disk is not None else 0, rin, rout, s.disk_power,
+                 s.checker_deg)
+
+
+def camera_struct(c: inputs.Camera) -> Camera:
+    return Camera(c.r, c.incl_deg, c.azim_deg, c.fov_deg, int(c.width), int(c.height))
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+ALL_FIELDS = ("cls", "b", "phi_end", "exit_dir", "r_hit", "steps", "path")
+
+
+def _alloc_out(n: int, fields, device):
+    import torch
+    shapes = {"cls": ((n,), torch.uint8), "b": ((n,), torch.float64),
+              "phi_end": ((n,), torch.float64), "exit_dir": ((n, 3), torch.float64),
+              "r_hit": ((n,), torch.float64), "steps": ((n,), torch.int32),
+              "path": ((n,), torch.uint8)}
+    t = {f: torch.empty(shapes[f][0], dtype=shapes[f][1], device=device) for f in fields}
+    ro = RayOut(*[t[f].data_ptr() if f in t else None for f in ALL_FIELDS])
+    return t, ro
+
+
+def trace_rays(origin, direction, scene: inputs.Scene, opt: Options | None = None,
+               fields=ALL_FIELDS, stream=None) -> dict:
+    """origin, direction: float64 CUDA tensors of shape (n, 3)."""
+    import torch
+    assert origin.dtype == torch.float64 and direction.dtype == torch.float64
+    origin = origin.contiguous()
+    direction = direction.contiguous()
+    n = origin.shape[0]
+    assert direction.shape[0] == n
+    if "cls" not in fields:
+        fields = ("cls",) + tuple(fields)
+    out, ro = _alloc_out(n, fields, origin.device)
+    sc = scene_struct(scene)
+    opt = opt or options()
+    check(lib().bh_trace_rays(origin.data_ptr(), direction.data_ptr(), n, C.byref(sc),
+                              C.byref(opt), C.byref(ro), _stream(stream)))
+    return out
+
+
+def render(camera: inputs.Camera, scene: inputs.Scene, opt: Options | None = None, rgba=None,
+           fields=None, stream=None, device="cuda"):
+    """Renders one frame.  Returns (rgba (H, W, 4) float32 tensor, per-pixel
+    dict or None).  ``fields`` selects per-pixel outputs (None: none)."""
+    import torch
+    H, W = camera.height, camera.width
+    if rgba is None:
+        rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
+    assert rgba.dtype == torch.float32 and rgba.is_contiguous() and rgba.numel() == H * W * 4
+    out, ro = (None, None)
+    if fields:
+        out, ro = _alloc_out(H * W, fields, rgba.device)
+    cam = camera_struct(camera)
+    sc = scene_struct(scene)
+    opt = opt or options()
+    check(lib().bh_render(C.byref(cam), C.byref(sc), C.byref(opt), rgba.data_ptr(),
+                          C.byref(ro) if ro is not None else None, _stream(stream)))
+    return rgba, out
+
+
+def reserve(n: int) -> None:
+    check(lib().bh_reserve(int(n)))
+
+
+def last_counts(stream=None) -> dict:
+    arr = (C.c_int64 * 4)()
+    check(lib().bh_last_counts(arr, _stream(stream)))
+    return {"setup": arr[0], "fp64": arr[1], "fp32": arr[2], "surrogate": arr[3]}
+
+
+KERNEL_CLASSES = ("setup", "integrate", "shade", "surrogate")
+
+
+def timing_enable(on: bool = True) -> None:
+    check(lib().bh_timing_enable(1 if on else 0))
+
+
+def timing_read() -> dict:
+    """{class: (summed ms, launches)} since the previous read."""
+    ms = (C.c_double * 4)()
+    n = (C.c_int64 * 4)()
+    check(lib().bh_timing_read(ms, n))
+    return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def shutdown() -> None:
+    check(lib().bh_shutdown())

@@ -1,0 +1,414 @@
+// C ABI of libbh: argument validation, the per-device workspace and the
+// launch sequence of a trace or render.  See include/bh.h for the contract.
+#include "bh.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "bh_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+bh_status fail(bh_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+bh_status hip_fail(hipError_t e, const char* what) {
+    return fail(BH_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Per-device workspace.  Grows on demand; never shrinks until bh_shutdown.
+struct Workspace {
+    int64_t cap = 0;
+    void* base = nullptr;
+    bh::Work w{};
+    unsigned long long* counts = nullptr;  // 4 counters for bh_last_counts
+    int64_t last_n = 0;
+    int cus = 0;
+};
+
+std::mutex g_mu;
+std::vector<Workspace> g_ws;
+
+// Launch timing (bh_timing_*): event pairs per launch, pooled.
+struct Timed {
+    int cls;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<Timed> g_timed;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records the start event of a timed launch; returns the slot or -1.
+int timing_begin(int cls, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return -1;
+    Timed t{cls, take_event(), take_event()};
+    if (!t.a || !t.b) return -1;
+    if (hipEventRecord(t.a, s) != hipSuccess) return -1;
+    g_timed.push_back(t);
+    return (int)g_timed.size() - 1;
+}
+
+void timing_end(int slot, hipStream_t s) {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    (void)hipEventRecord(g_timed[slot].b, s);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    Workspace& ws = g_ws[dev];
+    if (ws.cus == 0) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        ws.cus = cus > 0 ? cus : 256;
+    }
+    if (n > ws.cap || ws.base == nullptr) {
+        int64_t cap = n > 4096 ? n : 4096;
+        // per ray: u0, w0, phi1, phi_end, r_hit (8 B each), steps, q64 (4 B each), cls, path
+        const size_t sz8 = align256((size_t)cap * 8), sz4 = align256((size_t)cap * 4),
+                     sz1 = align256((size_t)cap);
+        const size_t total = 5 * sz8 + 2 * sz4 + 2 * sz1 + 256 + 256;
+        if (ws.base) {
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(ws.base);
+            ws.base = nullptr;
+            ws.cap = 0;
+        }
+        void* p = nullptr;
+        e = hipMalloc(&p, total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BH_ERR_NOMEM, "workspace of %zu bytes: %s", total, hipGetErrorString(e));
+        }
+        char* c = (char*)p;
+        ws.w.u0 = (double*)c; c += sz8;
+        ws.w.w0 = (double*)c; c += sz8;
+        ws.w.phi1 = (double*)c; c += sz8;
+        ws.w.phi_end = (double*)c; c += sz8;
+        ws.w.r_hit = (double*)c; c += sz8;
+        ws.w.steps = (int32_t*)c; c += sz4;
+        ws.w.q64 = (int32_t*)c; c += sz4;
+        ws.w.cls = (uint8_t*)c; c += sz1;
+        ws.w.path = (uint8_t*)c; c += sz1;
+        ws.w.ctr = (int32_t*)c; c += 256;
+        ws.counts = (unsigned long long*)c;
+        ws.base = p;
+        ws.cap = cap;
+    }
+    *out = &ws;
+    return BH_OK;
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+bh_status check_scene(const bh_scene* sc) {
+    if (!sc) return fail(BH_ERR_ARG, "scene is NULL");
+    if (!(isfinite(sc->M) && sc->M >= 0.0)) return fail(BH_ERR_ARG, "M must be finite and >= 0");
+    if (!finite_pos(sc->r_sky)) return fail(BH_ERR_ARG, "r_sky must be > 0");
+    if (!finite_pos(sc->checker_deg)) return fail(BH_ERR_ARG, "checker_deg must be > 0");
+    if (sc->has_disk) {
+        if (!(finite_pos(sc->disk_rin) && isfinite(sc->disk_rout) && sc->disk_rin < sc->disk_rout))
+            return fail(BH_ERR_ARG, "disk needs 0 < r_in < r_out");
+        if (!isfinite(sc->disk_power)) return fail(BH_ERR_ARG, "disk_power must be finite");
+    }
+    return BH_OK;
+}
+
+bh_status check_opt(const bh_options* o) {
+    if (!o) return fail(BH_ERR_ARG, "options is NULL");
+    if (o->precision != BH_FP64 && o->precision != BH_FP32)
+        return fail(BH_ERR_ARG, "precision must be BH_FP64 or BH_FP32");
+    if (!finite_pos(o->rtol) || !finite_pos(o->rtol_fp32))
+        return fail(BH_ERR_ARG, "tolerances must be > 0");
+    if (!isfinite(o->atol)) return fail(BH_ERR_ARG, "atol must be finite");
+    if (!(isfinite(o->band_halfwidth) && o->band_halfwidth >= 0.0))
+        return fail(BH_ERR_ARG, "band_halfwidth must be >= 0");
+    if (!finite_pos(o->h0) || !finite_pos(o->hmax) || !finite_pos(o->max_phi))
+        return fail(BH_ERR_ARG, "h0, hmax and max_phi must be > 0");
+    if (o->max_steps < 1) return fail(BH_ERR_ARG, "max_steps must be >= 1");
+    if (o->grid_blocks < 0 || o->chunk < 0) return fail(BH_ERR_ARG, "launch shape must be >= 0");
+    if (o->chunk % 64 != 0) return fail(BH_ERR_ARG, "chunk must be a multiple of 64");
+    return BH_OK;
+}
+
+bh::DevScene dev_scene(const bh_scene* sc) {
+    bh::DevScene d;
+    d.M = sc->M;
+    d.r_sky = sc->r_sky;
+    d.u_sky = 1.0 / sc->r_sky;
+    d.has_disk = sc->has_disk ? 1 : 0;
+    d.rin = sc->has_disk ? sc->disk_rin : 0.0;
+    d.rout = sc->has_disk ? sc->disk_rout : 0.0;
+    d.power = sc->has_disk ? sc->disk_power : 0.0;
+    d.cell_rad = sc->checker_deg * kPi / 180.0;
+    return d;
+}
+
+bh::DevTol dev_tol(const bh_options* o, const bh_scene* sc) {
+    bh::DevTol t;
+    t.rtol64 = o->rtol;
+    t.atol64 = o->atol > 0.0 ? o->atol : o->rtol / sc->r_sky;
+    t.rtol32 = (float)o->rtol_fp32;
+    t.atol32 = (float)(o->rtol_fp32 / sc->r_sky);
+    t.h0 = o->h0;
+    t.hmax = o->hmax;
+    t.max_phi = o->max_phi;
+    t.newton64 = 1e-15;
+    t.newton32 = 1e-7f;
+    t.max_steps = o->max_steps;
+    return t;
+}
+
+bh::DevRoute dev_route(const bh_options* o, const bh_scene* sc) {
+    bh::DevRoute r;
+    r.precision = o->precision;
+    r.analytic_capture = o->analytic_capture ? 1 : 0;
+    r.band = o->band_halfwidth * sc->M;
+    return r;
+}
+
+bh::Out dev_out(const bh_ray_out* o) {
+    bh::Out d{};
+    if (o) {
+        d.cls = o->cls;
+        d.b = o->b;
+        d.phi_end = o->phi_end;
+        d.exit_dir = o->exit_dir;
+        d.r_hit = o->r_hit;
+        d.steps = o->steps;
+        d.path = o->path;
+    }
+    return d;
+}
+
+int auto_grid(const Workspace& ws, int64_t n, const bh_options* o) {
+    int g = o->grid_blocks > 0 ? o->grid_blocks : ws.cus * 8;
+    const int64_t need = (n + 255) / 256;
+    if ((int64_t)g > need) g = (int)(need > 0 ? need : 1);
+    return g;
+}
+
+int auto_chunk(const bh_options* o) { return o->chunk > 0 ? o->chunk : 128; }
+
+// The shared sequence: reset counters, set-up, integrate, shade.
+bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const bh_scene* scene,
+              const bh_options* opt, float* rgba, const bh_ray_out* out, hipStream_t stream) {
+    Workspace* ws = nullptr;
+    bh_status st = get_workspace(src.n, stream, &ws);
+    if (st != BH_OK) return st;
+    const bh::DevScene sc = dev_scene(scene);
+    const bh::DevTol tol = dev_tol(opt, scene);
+    const bh::DevRoute rt = dev_route(opt, scene);
+    bh::Work w = ws->w;
+    if (!explicit_u0) w.u0 = nullptr;
+    hipError_t e = bh::launch_reset(w.ctr, stream);
+    if (e != hipSuccess) return hip_fail(e, "reset");
+    int t = timing_begin(0, stream);
+    e = bh::launch_setup(src, sc, rt, w, out ? out->b : nullptr, stream);
+    timing_end(t, stream);
+    if (e != hipSuccess) return hip_fail(e, "setup");
+    t = timing_begin(1, stream);
+    e = bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w,
+                             auto_grid(*ws, src.n, opt), auto_chunk(opt), stream);
+    timing_end(t, stream);
+    if (e != hipSuccess) return hip_fail(e, "integrate");
+    t = timing_begin(2, stream);
+    e = bh::launch_shade(src, sc, w, rgba, dev_out(out), stream);
+    timing_end(t, stream);
+    if (e != hipSuccess) return hip_fail(e, "shade");
+    ws->last_n = src.n;
+    return BH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bh_status bh_default_options(bh_options* o) {
+    if (!o) return fail(BH_ERR_ARG, "options is NULL");
+    memset(o, 0, sizeof *o);
+    o->precision = BH_FP64;
+    o->rtol = 1e-10;
+    o->atol = 0.0;
+    o->rtol_fp32 = 1e-6;
+    o->band_halfwidth = 0.05;
+    o->h0 = 1e-2;
+    o->hmax = 1.0;
+    o->max_phi = 8.0 * kPi;
+    o->max_steps = 1000000;
+    o->analytic_capture = 1;
+    o->grid_blocks = 0;
+    o->chunk = 0;
+    return BH_OK;
+}
+
+bh_status bh_trace_rays(const double* origin, const double* dir, int64_t n, const bh_scene* scene,
+                        const bh_options* opt, const bh_ray_out* out, void* stream) {
+    if (n < 0) return fail(BH_ERR_ARG, "n must be >= 0");
+    if (n > INT32_MAX) return fail(BH_ERR_ARG, "n must be < 2^31");
+    bh_status st = check_scene(scene);
+    if (st != BH_OK) return st;
+    if ((st = check_opt(opt)) != BH_OK) return st;
+    if (n == 0) return BH_OK;
+    if (!out || !out->cls) return fail(BH_ERR_ARG, "out->cls is required");
+    if (!origin || !dir) return fail(BH_ERR_ARG, "origin and dir are required");
+    bh::Source src{};
+    src.n = n;
+    src.origin = origin;
+    src.dir = dir;
+    return run(src, true, 0.0, scene, opt, nullptr, out, (hipStream_t)stream);
+}
+
+bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
+                    float* rgba, const bh_ray_out* per_pixel, void* stream) {
+    if (!cam) return fail(BH_ERR_ARG, "camera is NULL");
+    bh_status st = check_scene(scene);
+    if (st != BH_OK) return st;
+    if ((st = check_opt(opt)) != BH_OK) return st;
+    if (!rgba) return fail(BH_ERR_ARG, "rgba is NULL");
+    if (cam->width < 1 || cam->height < 1) return fail(BH_ERR_ARG, "width and height must be >= 1");
+    const int64_t n = (int64_t)cam->width * cam->height;
+    if (n > INT32_MAX) return fail(BH_ERR_ARG, "image must have < 2^31 pixels");
+    if (!(isfinite(cam->r) && cam->r > 3.0 * scene->M))
+        return fail(BH_ERR_ARG, "camera must be outside the photon sphere (r > 3M)");
+    if (!(cam->r < scene->r_sky)) return fail(BH_ERR_ARG, "camera must be inside the sky sphere");
+    if (!(isfinite(cam->fov_deg) && cam->fov_deg > 0.0 && cam->fov_deg < 180.0))
+        return fail(BH_ERR_ARG, "fov_deg must be in (0, 180)");
+    if (!isfinite(cam->incl_deg) || !isfinite(cam->azim_deg))
+        return fail(BH_ERR_ARG, "camera angles must be finite");
+
+    // Camera basis (per frame): position, forward = -position, up = -e_theta,
+    // right = forward x up.
+    const double inc = cam->incl_deg * kPi / 180.0, az = cam->azim_deg * kPi / 180.0;
+    const double ph[3] = {sin(inc) * cos(az), sin(inc) * sin(az), cos(inc)};
+    bh::Source src{};
+    src.n = n;
+    bh::DevCam& c = src.cam;
+    for (int k = 0; k < 3; ++k) {
+        c.pos[k] = cam->r * ph[k];
+        c.fwd[k] = -ph[k];
+    }
+    c.up[0] = -cos(inc) * cos(az);
+    c.up[1] = -cos(inc) * sin(az);
+    c.up[2] = sin(inc);
+    c.right[0] = c.fwd[1] * c.up[2] - c.fwd[2] * c.up[1];
+    c.right[1] = c.fwd[2] * c.up[0] - c.fwd[0] * c.up[2];
+    c.right[2] = c.fwd[0] * c.up[1] - c.fwd[1] * c.up[0];
+    c.tan_half = tan(0.5 * cam->fov_deg * kPi / 180.0);
+    c.W = cam->width;
+    c.H = cam->height;
+    return run(src, false, 1.0 / cam->r, scene, opt, rgba, per_pixel, (hipStream_t)stream);
+}
+
+bh_status bh_reserve(int64_t n) {
+    if (n < 0 || n > INT32_MAX) return fail(BH_ERR_ARG, "n out of range");
+    Workspace* ws = nullptr;
+    return get_workspace(n, nullptr, &ws);
+}
+
+bh_status bh_last_counts(int64_t counts[4], void* stream) {
+    if (!counts) return fail(BH_ERR_ARG, "counts is NULL");
+    Workspace* ws = nullptr;
+    bh_status st = get_workspace(0, (hipStream_t)stream, &ws);
+    if (st != BH_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemsetAsync(ws->counts, 0, 4 * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    if (ws->last_n > 0) {
+        e = bh::launch_count_paths(ws->last_n, ws->w, ws->counts, s);
+        if (e != hipSuccess) return hip_fail(e, "count");
+    }
+    unsigned long long h[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(h, ws->counts, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (int k = 0; k < 4; ++k) counts[k] = (int64_t)h[k];
+    return BH_OK;
+}
+
+bh_status bh_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return BH_OK;
+}
+
+bh_status bh_timing_read(double ms[4], int64_t launches[4]) {
+    if (!ms || !launches) return fail(BH_ERR_ARG, "ms and launches are required");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    bh_status st = BH_OK;
+    for (Timed& t : g_timed) {
+        float v = 0.f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&v, t.a, t.b);
+        if (e != hipSuccess && st == BH_OK) st = hip_fail(e, "hipEventElapsedTime");
+        if (t.cls >= 0 && t.cls < 4) {
+            ms[t.cls] += v;
+            launches[t.cls] += 1;
+        }
+        g_event_pool.push_back(t.a);
+        g_event_pool.push_back(t.b);
+    }
+    g_timed.clear();
+    return st;
+}
+
+bh_status bh_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (size_t d = 0; d < g_ws.size(); ++d) {
+        if (!g_ws[d].base) continue;
+        (void)hipSetDevice((int)d);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(g_ws[d].base);
+        g_ws[d] = Workspace{};
+    }
+    (void)hipSetDevice(cur);
+    return BH_OK;
+}
+
+const char* bh_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal definitions shared by the host runtime and the kernels of libbh.
+// Not part of the public ABI (include/bh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bh {
+
+constexpr int kBlock = 256;   // threads per block for every kernel
+constexpr int kWave = 64;     // CDNA wavefront
+
+// Scene constants in the form the kernels use.
+struct DevScene {
+    double M;
+    double r_sky, u_sky;
+    double rin, rout, power;
+    double cell_rad;          // checker cell in radians
+    int has_disk;
+};
+
+// Integrator tolerances and caps.
+struct DevTol {
+    double rtol64, atol64;
+    float rtol32, atol32;
+    double h0, hmax, max_phi;
+    double newton64;          // Newton stop on |dh| for the sky crossing
+    float newton32;
+    int max_steps;
+};
+
+// Camera basis for one frame, computed once per frame by the host runtime.
+struct DevCam {
+    double pos[3];            // camera position C
+    double fwd[3], right[3], up[3];
+    double tan_half;          // tan(vfov/2)
+    int W, H;
+};
+
+// Routing policy applied at set-up.
+struct DevRoute {
+    int precision;            // BH_FP64 / BH_FP32
+    int analytic_capture;
+    double band;              // half-width of the critical band, absolute units
+};
+
+// Per-ray workspace (structure of arrays, capacity >= rays of the call).
+struct Work {
+    double* u0;               // 1/|origin| per ray (explicit-ray mode only)
+    double* w0;               // du/dphi at the start
+    double* phi1;             // first disk-plane crossing angle, +inf if none
+    uint8_t* cls;
+    uint8_t* path;
+    double* phi_end;
+    double* r_hit;
+    int32_t* steps;
+    int32_t* q64;             // FP64 band queue (FP32 mode)
+    int32_t* ctr;             // [0] q64 size, [1] q64 head, [2] main head, [3..7] spare
+};
+
+// Optional caller-owned outputs (mirrors bh_ray_out).
+struct Out {
+    uint8_t* cls;
+    double* b;
+    double* phi_end;
+    double* exit_dir;
+    double* r_hit;
+    int32_t* steps;
+    uint8_t* path;
+};
+
+// Ray source for set-up and shading: a camera, or explicit origin/direction arrays.
+struct Source {
+    int64_t n;
+    const double* origin;     // n*3, or NULL for camera mode
+    const double* dir;        // n*3
+    DevCam cam;
+};
+
+// Launch helpers (defined in bh_kernels.hip).
+hipError_t launch_reset(int32_t* ctr, hipStream_t s);
+hipError_t launch_setup(const Source& src, const DevScene& sc, const DevRoute& rt, const Work& w,
+                        double* out_b, hipStream_t s);
+hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, const DevScene& sc,
+                            const DevTol& tol, int precision, const Work& w, int grid_blocks,
+                            int chunk, hipStream_t s);
+hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
+                        const Out& out, hipStream_t s);
+hipError_t launch_count_paths(int64_t n, const Work& w, unsigned long long* counts, hipStream_t s);
+
+}  // namespace bh

@@ -1,0 +1,104 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point include/bh.h declares, fills defaults, and rejects bad arguments
+before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2507_16165_amd import api, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(bh_\w+)\s*\(", txt, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = api.lib()
+    names = declared_symbols()
+    assert {"bh_trace_rays", "bh_render", "bh_default_options", "bh_last_error"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
+
+
+def test_defaults():
+    o = api.options()
+    assert o.precision == api.FP64 and o.rtol == 1e-10 and o.atol == 0.0
+    assert o.rtol_fp32 == 1e-6 and o.band_halfwidth == 0.05 and o.max_steps == 1000000
+    assert abs(o.max_phi - 8 * 3.141592653589793) < 1e-12 and o.analytic_capture == 1
+
+
+def _render(cam, sc, opt=None, rgba=1):
+    L = api.lib()
+    c = api.camera_struct(cam)
+    s = api.scene_struct(sc)
+    o = opt or api.options()
+    return L.bh_render(C.byref(c), C.byref(s), C.byref(o), C.c_void_p(rgba), None, None)
+
+
+@pytest.mark.parametrize("cam,sc,msg", [
+    (inputs.Camera(2.5, 90, 0, 60, 8, 8), inputs.Scene(M=1.0), "photon sphere"),
+    (inputs.Camera(30, 90, 0, 0.0, 8, 8), inputs.Scene(M=1.0), "fov"),
+    (inputs.Camera(30, 90, 0, 180.0, 8, 8), inputs.Scene(M=1.0), "fov"),
+    (inputs.Camera(30, 90, 0, 60, 0, 8), inputs.Scene(M=1.0), "width"),
+    (inputs.Camera(30, 90, 0, 60, 8, 8), inputs.Scene(M=-1.0), "M must"),
+    (inputs.Camera(30, 90, 0, 60, 8, 8), inputs.Scene(M=1.0, disk=(20.0, 6.0)), "disk"),
+    (inputs.Camera(3000, 90, 0, 60, 8, 8), inputs.Scene(M=1.0), "sky"),
+])
+def test_render_rejects_bad_arguments(cam, sc, msg):
+    st = _render(cam, sc)
+    assert st == api.BH_ERR_ARG
+    assert msg in api.lib().bh_last_error().decode()
+
+
+def test_render_rejects_null_and_bad_options():
+    cam, sc = inputs.Camera(30, 90, 0, 60, 8, 8), inputs.Scene(M=1.0)
+    assert _render(cam, sc, rgba=0) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(precision=7)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(rtol=-1.0)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(chunk=100)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(max_steps=0)) == api.BH_ERR_ARG
+    L = api.lib()
+    assert L.bh_render(None, None, None, None, None, None) == api.BH_ERR_ARG
+    assert L.bh_default_options(None) == api.BH_ERR_ARG
+
+
+def test_trace_rays_argument_checks():
+    L = api.lib()
+    s = api.scene_struct(inputs.Scene(M=1.0))
+    o = api.options()
+    out = api.RayOut()
+    # no cls output
+    assert L.bh_trace_rays(None, None, 4, C.byref(s), C.byref(o), C.byref(out), None) == api.BH_ERR_ARG
+    # n = 0 is a no-op that touches nothing, even with no outputs
+    assert L.bh_trace_rays(None, None, 0, C.byref(s), C.byref(o), C.byref(out), None) == api.BH_OK
+    out.cls = 1
+    assert L.bh_trace_rays(None, None, -1, C.byref(s), C.byref(o), C.byref(out), None) == api.BH_ERR_ARG
+    assert L.bh_trace_rays(None, None, 4, C.byref(s), C.byref(o), C.byref(out), None) == api.BH_ERR_ARG
+    # n = 0 is a no-op that touches nothing
+    assert L.bh_trace_rays(None, None, 0, C.byref(s), C.byref(o), C.byref(out), None) == api.BH_OK
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(api, "_lib", None)
+    monkeypatch.setattr(api, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        api.lib()
+
+
+def test_output_marshalling_on_host_tensors():
+    """The binding's output allocation and pointer packing (host tensors)."""
+    t, ro = api._alloc_out(10, api.ALL_FIELDS, "cpu")
+    assert t["exit_dir"].shape == (10, 3) and t["cls"].dtype.itemsize == 1
+    assert ro.exit_dir == t["exit_dir"].data_ptr() and ro.steps == t["steps"].data_ptr()
+    t, ro = api._alloc_out(4, ("cls",), "cpu")
+    assert ro.b is None and ro.cls == t["cls"].data_ptr()

@@ -1,0 +1,217 @@
+"""GPU path (through the C ABI) against the CPU FP64 oracle, element by element.
+
+Workloads: the 64x64 plain frame, the 1024x1024 disk frame (FP64 and FP32 +
+FP64 band), 4K orbit frames (sampled rows at full size, in the default launch
+shape the benchmark times), random ray sets, and edge cases.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2507_16165_amd import inputs
+from parity import B_CRIT, compare, compare_rgba
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2507_16165_amd import api
+    api.lib()
+    return api
+
+
+def ref_scene(ref, s: inputs.Scene):
+    return ref.scene(s.M, r_sky=s.r_sky, disk=s.disk, disk_power=s.disk_power,
+                     checker_deg=s.checker_deg)
+
+
+def ref_camera(ref, c: inputs.Camera):
+    return ref.camera(c.r, c.incl_deg, c.azim_deg, c.fov_deg, c.width, c.height)
+
+
+def np_out(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def gpu_render(bh, frame, precision, **kw):
+    import torch
+    opt = bh.options(precision=precision, **kw)
+    rgba, out = bh.render(frame.camera, frame.scene, opt, fields=bh.ALL_FIELDS)
+    torch.cuda.synchronize()
+    return rgba.cpu().numpy(), np_out(out)
+
+
+def oracle_rows(ref, frame, rows, rtol=1e-10):
+    """Oracle on a set of image rows (full image arrays; other rows zero)."""
+    cam, sc = ref_camera(ref, frame.camera), ref_scene(ref, frame.scene)
+    W, H = frame.camera.width, frame.camera.height
+    rgba = np.zeros((H, W, 4), np.float32)
+    mask = np.zeros(H * W, bool)
+    acc = None
+    for r0 in rows:
+        img, rays = ref.render(cam, sc, ref.options(rtol=rtol), rows=(r0, r0 + 1))
+        rgba[r0] = img[r0]
+        sl = slice(r0 * W, (r0 + 1) * W)
+        mask[sl] = True
+        if acc is None:
+            acc = rays
+        else:
+            for f in ("cls", "b", "phi_end", "exit_dir", "r_hit", "n_acc", "n_rej", "e_drift"):
+                getattr(acc, f)[sl] = getattr(rays, f)[sl]
+    return rgba, acc, mask
+
+
+# ---------------------------------------------------------------------------
+def test_plain64_fp64_full_image(bh, ref):
+    f = inputs.plain_64()
+    rgba, out = gpu_render(bh, f, bh.FP64)
+    r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
+    s = compare(r_rays, out, f.scene, "fp64")
+    assert s["n"] == 4096 and s["captured"] >= 290
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, "fp64")
+    assert (out["cls"] == bh.CAPTURED).sum() == 300  # closed-form shadow count
+
+
+@pytest.mark.parametrize("size", [200, 1024])
+def test_disk_frame_fp64(bh, ref, size):
+    f = inputs.disk_1024(size)
+    rgba, out = gpu_render(bh, f, bh.FP64)
+    H = f.camera.height
+    rows = range(H) if size <= 200 else sorted(set(np.linspace(0, H - 1, 40).astype(int)) | {H // 2})
+    r_rgba, r_rays, mask = oracle_rows(ref, f, list(rows))
+    s = compare(r_rays, out, f.scene, "fp64", mask=mask)
+    assert s["disk"] > 0 and s["sky"] > 0
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, "fp64", mask=mask)
+
+
+@pytest.mark.parametrize("size", [200, 1024])
+def test_disk_frame_fp32_band(bh, ref, size):
+    f = inputs.disk_1024(size)
+    rgba, out = gpu_render(bh, f, bh.FP32)
+    H = f.camera.height
+    rows = range(H) if size <= 200 else sorted(set(np.linspace(0, H - 1, 40).astype(int)) | {H // 2})
+    r_rgba, r_rays, mask = oracle_rows(ref, f, list(rows))
+    s = compare(r_rays, out, f.scene, "fp32", mask=mask)
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, "fp32", mask=mask)
+    # the critical band went through the FP64 integrator, the rest through FP32
+    band = np.abs(out["b"] - B_CRIT * f.scene.M) < 0.05 * f.scene.M
+    assert np.all(out["path"][band] == bh.PATH_FP64)
+    assert np.all(out["path"][~band & (out["path"] != bh.PATH_NONE)] == bh.PATH_FP32)
+    assert s["max_angle"] <= 1e-4
+
+
+@pytest.mark.parametrize("k", [0, 7])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_orbit4k_frame_sampled_rows(bh, ref, k, precision):
+    """Full 3840x2160 frames of the 16-frame orbit, default launch shape;
+    the oracle checks 12 rows spread over the frame."""
+    f = inputs.orbit_4k()[k]
+    rgba, out = gpu_render(bh, f, bh.FP64 if precision == "fp64" else bh.FP32)
+    H = f.camera.height
+    rows = sorted(set(np.linspace(0, H - 1, 11).astype(int)) | {H // 2})
+    r_rgba, r_rays, mask = oracle_rows(ref, f, rows)
+    compare(r_rays, out, f.scene, precision, mask=mask)
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, precision, mask=mask)
+    # whole-frame properties: every pixel written, alpha 1, classes valid
+    assert np.all(rgba[..., 3] == 1.0)
+    assert np.all(out["cls"] <= 3)
+
+
+@pytest.mark.parametrize("M,disk", [(1.0, (6.0, 30.0)), (0.5, None), (0.0, (2.0, 40.0))])
+def test_trace_rays_random(bh, ref, M, disk):
+    import torch
+    sc = inputs.Scene(M=M, r_sky=1000.0, disk=disk)
+    o, d = inputs.random_rays(20000, seed=int(10 + 3 * M), r_min=max(3.5 * M, 5.0), r_max=200.0,
+                              aim_scale=15.0)
+    out = np_out(bh.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), sc))
+    r = ref.trace_rays(o, d, ref_scene(ref, sc))
+    compare(r, out, sc, "fp64")
+    out32 = np_out(bh.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), sc,
+                                 bh.options(precision=bh.FP32)))
+    compare(r, out32, sc, "fp32")
+
+
+def test_trace_rays_degenerate(bh, ref):
+    import torch
+    sc = inputs.Scene(M=1.0, r_sky=1000.0)
+    o = np.array([[50.0, 0, 0], [50.0, 0, 0], [2.9, 0, 0], [2000.0, 0, 0], [np.nan, 0, 0],
+                  [50.0, 0, 0], [0, 0, 40.0]])
+    d = np.array([[-1.0, 0, 0], [1.0, 0, 0], [0, 1.0, 0], [0, 1.0, 0], [0, 1.0, 0], [0, 0, 0],
+                  [0.1, 0, -1]])
+    out = np_out(bh.trace_rays(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), sc))
+    r = ref.trace_rays(o, d, ref_scene(ref, sc))
+    np.testing.assert_array_equal(out["cls"], r.cls)
+    np.testing.assert_allclose(out["exit_dir"][:2], r.exit_dir[:2], atol=1e-15)
+    # empty batch
+    e = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    assert bh.trace_rays(e, e, sc)["cls"].numel() == 0
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (67, 13), (5, 300)])
+def test_ragged_and_tiny_images(bh, ref, W, H):
+    f = inputs.Frame(inputs.Camera(25.0, 63.0, 30.0, 70.0, W, H), inputs.scene_in_m(1.0, (6.0, 20.0)))
+    rgba, out = gpu_render(bh, f, bh.FP64)
+    r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
+    compare(r_rays, out, f.scene, "fp64")
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, "fp64")
+
+
+def test_flat_space_render(bh, ref):
+    f = inputs.Frame(inputs.Camera(30.0, 90.0, 0.0, 60.0, 48, 32),
+                     inputs.Scene(M=0.0, r_sky=1000.0, disk=(2.0, 12.0)))
+    rgba, out = gpu_render(bh, f, bh.FP64)
+    r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
+    compare(r_rays, out, f.scene, "fp64")
+    assert not np.any(out["cls"] == bh.CAPTURED)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_schedule_invariance(bh, precision):
+    """Each ray's arithmetic is independent of the launch shape and queue
+    order: results are bit-identical across grid sizes and chunk sizes (the
+    race test for the work queue)."""
+    f = inputs.disk_1024(256)
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    base_rgba, base = gpu_render(bh, f, p)
+    for g, c in [(1, 64), (7, 64), (64, 1024), (3, 192)]:
+        rgba, out = gpu_render(bh, f, p, grid_blocks=g, chunk=c)
+        np.testing.assert_array_equal(rgba, base_rgba)
+        for k in ("cls", "phi_end", "r_hit", "steps", "path"):
+            np.testing.assert_array_equal(out[k], base[k])
+
+
+def test_step_caps(bh, ref):
+    """max_steps and max_phi caps give UNRESOLVED, as in the oracle."""
+    f = inputs.plain_64()
+    _, out = gpu_render(bh, f, bh.FP64, max_steps=5, analytic_capture=0)
+    assert np.all(out["cls"] == bh.UNRESOLVED)
+    assert np.all(out["steps"] == 5)
+    _, r = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene), ref.options(max_phi=1.0))
+    _, out = gpu_render(bh, f, bh.FP64, max_phi=1.0, analytic_capture=0)
+    np.testing.assert_array_equal(out["cls"], r.cls)
+
+
+def test_step_counts_track_oracle(bh, ref):
+    """Same controller: mean step evaluations per ray within 8% of the
+    oracle's accepted + rejected count (the GPU count also includes the <= 3
+    sky-crossing refinement steps)."""
+    f = inputs.disk_1024(128)
+    _, out = gpu_render(bh, f, bh.FP64, analytic_capture=0)
+    _, r = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
+    g = out["steps"].mean()
+    o = (r.n_acc + r.n_rej).mean()
+    assert abs(g / o - 1.0) < 0.08, (g, o)
+
+
+def test_counts(bh):
+    import torch
+    f = inputs.plain_64()
+    bh.render(f.camera, f.scene, bh.options(precision=bh.FP32))
+    c = bh.last_counts()
+    assert sum(c.values()) == 4096
+    assert 250 < c["setup"] <= 300  # analytic captures (below the band)
+    assert c["fp64"] > 0 and c["fp32"] > 3000
