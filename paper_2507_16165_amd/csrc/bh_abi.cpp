@@ -98,10 +98,11 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
     }
     if (n > ws.cap || ws.base == nullptr) {
         int64_t cap = n > 4096 ? n : 4096;
-        // per ray: u0, w0, phi1, phi_end, r_hit (8 B each), steps, q64 (4 B each), cls, path
-        const size_t sz8 = align256((size_t)cap * 8), sz4 = align256((size_t)cap * 4),
-                     sz1 = align256((size_t)cap);
-        const size_t total = 5 * sz8 + 2 * sz4 + 2 * sz1 + 256 + 256;
+        // per ray: u0 (8 B), rec, res, q64rec (16 B each), clst, q64 (4 B each), path (1 B)
+        const size_t sz16 = align256((size_t)cap * 16), sz8 = align256((size_t)cap * 8),
+                     sz4 = align256((size_t)cap * 4), sz1 = align256((size_t)cap);
+        const size_t szc = align256(sizeof(int32_t) * bh::kCtrInts);
+        const size_t total = 3 * sz16 + sz8 + 2 * sz4 + sz1 + szc + 256;
         if (ws.base) {
             e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -118,16 +119,14 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
             return fail(BH_ERR_NOMEM, "workspace of %zu bytes: %s", total, hipGetErrorString(e));
         }
         char* c = (char*)p;
+        ws.w.rec = (double2*)c; c += sz16;
+        ws.w.res = (double2*)c; c += sz16;
+        ws.w.q64rec = (double2*)c; c += sz16;
         ws.w.u0 = (double*)c; c += sz8;
-        ws.w.w0 = (double*)c; c += sz8;
-        ws.w.phi1 = (double*)c; c += sz8;
-        ws.w.phi_end = (double*)c; c += sz8;
-        ws.w.r_hit = (double*)c; c += sz8;
-        ws.w.steps = (int32_t*)c; c += sz4;
+        ws.w.clst = (int32_t*)c; c += sz4;
         ws.w.q64 = (int32_t*)c; c += sz4;
-        ws.w.cls = (uint8_t*)c; c += sz1;
         ws.w.path = (uint8_t*)c; c += sz1;
-        ws.w.ctr = (int32_t*)c; c += 256;
+        ws.w.ctr = (int32_t*)c; c += szc;
         ws.counts = (unsigned long long*)c;
         ws.base = p;
         ws.cap = cap;
@@ -177,6 +176,8 @@ bh::DevScene dev_scene(const bh_scene* sc) {
     d.rin = sc->has_disk ? sc->disk_rin : 0.0;
     d.rout = sc->has_disk ? sc->disk_rout : 0.0;
     d.power = sc->has_disk ? sc->disk_power : 0.0;
+    d.urin = sc->has_disk ? 1.0 / sc->disk_rin : 0.0;
+    d.urout = sc->has_disk ? 1.0 / sc->disk_rout : 0.0;
     d.cell_rad = sc->checker_deg * kPi / 180.0;
     return d;
 }
@@ -218,14 +219,7 @@ bh::Out dev_out(const bh_ray_out* o) {
     return d;
 }
 
-int auto_grid(const Workspace& ws, int64_t n, const bh_options* o) {
-    int g = o->grid_blocks > 0 ? o->grid_blocks : ws.cus * 8;
-    const int64_t need = (n + 255) / 256;
-    if ((int64_t)g > need) g = (int)(need > 0 ? need : 1);
-    return g;
-}
-
-int auto_chunk(const bh_options* o) { return o->chunk > 0 ? o->chunk : 128; }
+int auto_chunk(const bh_options* o) { return o->chunk > 0 ? o->chunk : 256; }
 
 // The shared sequence: reset counters, set-up, integrate, shade.
 bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const bh_scene* scene,
@@ -245,8 +239,8 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "setup");
     t = timing_begin(1, stream);
-    e = bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w,
-                             auto_grid(*ws, src.n, opt), auto_chunk(opt), stream);
+    e = bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w, ws->cus,
+                             opt->grid_blocks, auto_chunk(opt), stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "integrate");
     t = timing_begin(2, stream);

@@ -15,6 +15,7 @@ struct DevScene {
     double M;
     double r_sky, u_sky;
     double rin, rout, power;
+    double urin, urout;       // 1/rin, 1/rout: the disk test runs on u = 1/r
     double cell_rad;          // checker cell in radians
     int has_disk;
 };
@@ -47,16 +48,23 @@ struct DevRoute {
 // Per-ray workspace (structure of arrays, capacity >= rays of the call).
 struct Work {
     double* u0;               // 1/|origin| per ray (explicit-ray mode only)
-    double* w0;               // du/dphi at the start
-    double* phi1;             // first disk-plane crossing angle, +inf if none
-    uint8_t* cls;
+    double2* rec;             // start record {w0, phi1}; w0 = NaN: not in the main queue
+    double2* res;             // result record {phi_end, r_hit}
+    int32_t* clst;            // class | (step evaluations << 3)
     uint8_t* path;
-    double* phi_end;
-    double* r_hit;
-    int32_t* steps;
-    int32_t* q64;             // FP64 band queue (FP32 mode)
-    int32_t* ctr;             // [0] q64 size, [1] q64 head, [2] main head, [3..7] spare
+    int32_t* q64;             // FP64 band queue (FP32 mode): ray indices ...
+    double2* q64rec;          // ... and their start records
+    int32_t* ctr;             // queue counters, kCtrInts ints (layout below)
 };
+
+// Queue counters (int32 indices into Work::ctr); each head sits on its own
+// 256-byte line.
+constexpr int kCtrStride = 64;
+constexpr int kSlices = 8;                              // main-queue slices
+constexpr int kCtrBandSize = 0;                         // FP64 band queue length
+constexpr int kCtrBand = kCtrStride;                    // band queue head
+constexpr int kCtrMain = 2 * kCtrStride;                // kSlices main-queue heads
+constexpr int kCtrInts = kCtrMain + kSlices * kCtrStride;
 
 // Optional caller-owned outputs (mirrors bh_ray_out).
 struct Out {
@@ -82,8 +90,8 @@ hipError_t launch_reset(int32_t* ctr, hipStream_t s);
 hipError_t launch_setup(const Source& src, const DevScene& sc, const DevRoute& rt, const Work& w,
                         double* out_b, hipStream_t s);
 hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, const DevScene& sc,
-                            const DevTol& tol, int precision, const Work& w, int grid_blocks,
-                            int chunk, hipStream_t s);
+                            const DevTol& tol, int precision, const Work& w, int cus,
+                            int grid_blocks, int chunk, hipStream_t s);
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
                         const Out& out, hipStream_t s);
 hipError_t launch_count_paths(int64_t n, const Work& w, unsigned long long* counts, hipStream_t s);

@@ -111,17 +111,20 @@ __device__ __forceinline__ double first_crossing(double a, double bz) {
 // captured in a graph).
 // ---------------------------------------------------------------------------
 __global__ void k_reset(int32_t* ctr) {
-    if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < kCtrInts; i += blockDim.x) ctr[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // Set-up and routing.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double nan_d() { return __builtin_nan(""); }
+
 __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRoute rt, Work w,
                                                   double* out_b) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = i < src.n;
     bool to_q64 = false;
+    double w0 = 0.0, phi1 = 0.0;
     if (valid) {
         double o[3], dv[3];
         source_ray(src, i, o, dv);
@@ -139,14 +142,13 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
             }
         } else if (B.ok) {
             const double u0 = 1.0 / B.r0;
-            const double w0 = -u0 * B.c / B.s;
+            w0 = -u0 * B.c / B.s;
             // First integral of Eq. (1): w^2 + u^2 - 2 M u^3 = 1/b^2.
             const double E0 = w0 * w0 + u0 * u0 - 2.0 * sc.M * u0 * u0 * u0;
             b = 1.0 / sqrt(E0);
             const double bc = kBcrit * sc.M;
-            w.w0[i] = w0;
             if (w.u0) w.u0[i] = u0;
-            w.phi1[i] = sc.has_disk ? first_crossing(B.e1[2], B.e2[2]) : __builtin_inf();
+            phi1 = sc.has_disk ? first_crossing(B.e1[2], B.e2[2]) : __builtin_inf();
             if (rt.analytic_capture && !sc.has_disk && B.c < 0.0 && b < bc - rt.band) {
                 cls = CAPTURED;  // below the potential peak: falls in, no disk to hit
             } else if (rt.precision == 1 && fabs(b - bc) < rt.band) {
@@ -157,11 +159,13 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
             }
         }
         w.path[i] = path;
+        // The main queue is the index range itself; its record marks rays
+        // that belong to another path (band, set-up only) with w0 = NaN.
+        const bool main = path != PATH_NONE && !to_q64;
+        w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
         if (path == PATH_NONE) {
-            w.cls[i] = cls;
-            w.phi_end[i] = phi_end;
-            w.r_hit[i] = 0.0;
-            w.steps[i] = 0;
+            w.res[i] = make_double2(phi_end, 0.0);
+            w.clst[i] = cls;
         }
         if (out_b) out_b[i] = b;
     }
@@ -171,9 +175,13 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
     if (m) {
         const int leader = __ffsll((unsigned long long)m) - 1;
         int base = 0;
-        if (lane_id() == leader) base = atomicAdd(&w.ctr[0], __popcll(m));
+        if (lane_id() == leader) base = atomicAdd(&w.ctr[kCtrBandSize], __popcll(m));
         base = __shfl(base, leader);
-        if (to_q64) w.q64[base + rank_in(m)] = (int32_t)i;
+        if (to_q64) {
+            const int slot = base + rank_in(m);
+            w.q64[slot] = (int32_t)i;
+            w.q64rec[slot] = make_double2(w0, phi1);
+        }
     }
 }
 
@@ -234,23 +242,23 @@ __device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T&
     ew = h * fma(e7, g7, fma(e6, g6, fma(e5, g5, fma(e4, g4, fma(e3, g3, e1 * g1)))));
 }
 
-// Step-size factor 0.9 err^(-1/5), evaluated in FP32 with the hardware
-// log2/exp2 (a heuristic; only the accept test needs full precision).
+// Step-size factor 0.9 err^(-1/5) without transcendental instructions: an
+// exponent-field estimate of err^(-1/5) (i_y = 1.2 * bits(1.0f) - bits(err)/5),
+// refined by one Newton step y <- y (6 - err y^5) / 5 (error ~1.5%; the factor
+// is a heuristic, only the accept test needs full precision).  NaN/inf errors
+// give a factor below 0.2, which the callers clamp to 0.2.
 __device__ __forceinline__ float step_factor(float err) {
-    return 0.9f * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
+    err = (err != err) ? 3.0e38f : fmaxf(err, 1e-30f);
+    const uint32_t i = __float_as_uint(err);
+    const float y = __uint_as_float(1278423859u - i / 5u);
+    const float y2 = y * y;
+    const float y5 = y2 * y2 * y;
+    return y * fmaf(-err, y5, 6.0f) * (0.9f / 5.0f);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent integrator.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Lane {
-    T u, w, g, h, hh;
-    double phi, phik;
-    int id, attempts, nsteps, it;
-    bool rej, refine, active;
-};
-
 struct IntegArgs {
     int64_t n;
     const double* u0;         // per-ray u0, or NULL (use u0_uniform)
@@ -261,176 +269,218 @@ struct IntegArgs {
     int chunk;
 };
 
-template <typename T>
-__device__ __forceinline__ void finish(const IntegArgs& a, Lane<T>& L, uint8_t cls, double phi,
-                                       double r_hit) {
-    a.w.cls[L.id] = cls;
-    a.w.phi_end[L.id] = phi;
-    a.w.r_hit[L.id] = r_hit;
-    a.w.steps[L.id] = L.nsteps;
-    L.active = false;
+// 1/x in FP64 from the hardware reciprocal estimate and one Newton step
+// (relative error ~1e-16; used for the Newton update of the sky crossing).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
 }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Drains one queue.  VIRTUAL: the queue is the index range [0, total) and a
-// ray is taken only if its set-up tag equals `tag`; otherwise queue[] holds
-// the ray indices.
+// Drains one queue.  VIRTUAL: the queue is the index range [0, total) and
+// the start records come from rec[id] (w0 = NaN: the ray is not for this
+// queue); otherwise queue[] holds ray indices and qrec[] their records.
+//
+// Each lane keeps the start record of its NEXT ray in registers: the loads
+// are issued one iteration ahead (step C, before the step arithmetic) and
+// consumed when the lane's ray ends (step A).  Positions are handed out per
+// wavefront from a chunk taken with one atomic.
+//
+// The step (B) is a predicated state machine: every lane evaluates one
+// Dormand-Prince step per iteration -- a normal trial step, or a Newton
+// re-step of the sky crossing -- and all outcomes (accept / reject, disk
+// landing, horizon, sky crossing, caps) are applied with selects, so the
+// wavefront stays converged except for the store of a finished ray.
 template <typename T, bool VIRTUAL>
-__device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue, int64_t total,
-                          int32_t* head, uint8_t tag, T rtol, T atol, T ntol) {
+__device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
+                          const double2* __restrict__ qrec, int64_t total, int32_t* heads,
+                          int nslices, T rtol, T atol, T ntol) {
     const int lane = lane_id();
     const T M3 = T(3.0 * a.sc.M);
     const double twoM = 2.0 * a.sc.M;
     const T usky = T(a.sc.u_sky);
     const T h0 = T(a.tol.h0), hmax = T(a.tol.hmax);
-    const double rin = a.sc.rin, rout = a.sc.rout;
+    const T urin = T(a.sc.urin), urout = T(a.sc.urout);
+    const double max_phi = a.tol.max_phi;
+    const int max_steps = a.tol.max_steps;
 
-    Lane<T> L;
-    L.active = false;
+    // ray state
+    T u = T(0), w = T(0), g = T(0), h = T(0), hh = T(0);
+    double phi = 0.0, phik = 0.0;
+    int id = 0, attempts = 0, nsteps = 0, it = 0;
+    bool rej = false, refine = false, active = false;
+    // prefetched next ray
+    int pf_id = 0;
+    double2 pf = make_double2(0.0, 0.0);
+    double pf_u0 = a.u0_uniform;
+    bool pf_valid = false;
     int64_t cnext = 0, cend = 0;
     bool drained = false;
+    int slice = (int)(blockIdx.x % (unsigned)nslices), dry = 0;
 
     for (;;) {
-        // ---- refill idle lanes from the wavefront's current chunk ---------
-        for (int round = 0; round < 2; ++round) {
-            const uint64_t need = __ballot(!L.active);
-            if (need == 0 || (drained && cnext >= cend)) break;
-            if (cnext >= cend) {
-                int base = 0;
-                if (lane == 0) base = atomicAdd(head, a.chunk);
-                base = __shfl(base, 0);
-                // base < 0: the 32-bit head wrapped after the queue drained
-                if (base < 0 || (int64_t)base >= total) {
-                    drained = true;
-                    break;
-                }
-                cnext = base;
-                cend = min((int64_t)base + a.chunk, total);
+        // ---- (A) an idle lane starts its prefetched ray --------------------
+        if (!active && pf_valid) {
+            pf_valid = false;
+            if (!VIRTUAL || pf.x == pf.x) {
+                id = pf_id;
+                u = T(pf_u0);
+                w = T(pf.x);
+                g = g_of(M3, u);
+                h = h0;
+                phi = 0.0;
+                phik = pf.y;
+                attempts = 0;
+                nsteps = 0;
+                it = 0;
+                rej = false;
+                refine = false;
+                active = true;
             }
-            const int nneed = __popcll(need);
-            const int rank = rank_in(need);
-            const int64_t avail = cend - cnext;
-            if (!L.active && rank < avail) {
-                const int64_t pos = cnext + rank;
-                const int id = VIRTUAL ? (int)pos : queue[pos];
-                if (!VIRTUAL || a.w.path[id] == tag) {
-                    L.id = id;
-                    L.u = T(a.u0 ? a.u0[id] : a.u0_uniform);
-                    L.w = T(a.w.w0[id]);
-                    L.g = g_of(M3, L.u);
-                    L.h = h0;
-                    L.phi = 0.0;
-                    L.phik = a.w.phi1[id];
-                    L.attempts = 0;
-                    L.nsteps = 0;
-                    L.it = 0;
-                    L.rej = false;
-                    L.refine = false;
-                    L.active = true;
-                }
-            }
-            cnext += min((int64_t)nneed, avail);
         }
-        if (__ballot(L.active) == 0) {
-            if (drained) break;
+        // ---- (C) lanes without a next ray fetch one (loads not awaited) ----
+        const uint64_t need = __ballot(!pf_valid);
+        if (need != 0 && !(drained && cnext >= cend)) {
+            // Chunk k of slice s covers positions [(k*nslices + s)*chunk, +chunk):
+            // the slices interleave over the queue, each with its own head
+            // counter (one atomic per chunk; separate counters spread the
+            // atomics of the whole chip over several addresses).  A wavefront
+            // starts on its block's slice and moves on when a slice is dry.
+            while (cnext >= cend && !drained) {
+                int k = 0;
+                if (lane == 0) k = atomicAdd(&heads[slice * kCtrStride], 1);
+                k = __shfl(k, 0);
+                const int64_t base = ((int64_t)k * nslices + slice) * a.chunk;
+                if (k >= 0 && base < total) {
+                    cnext = base;
+                    cend = min(base + a.chunk, total);
+                } else {
+                    slice = slice + 1 == nslices ? 0 : slice + 1;
+                    drained = ++dry >= nslices;
+                }
+            }
+            if (cnext < cend) {
+                const int rank = rank_in(need);
+                const int64_t avail = cend - cnext;
+                if (!pf_valid && rank < avail) {
+                    const int64_t pos = cnext + rank;
+                    pf_id = VIRTUAL ? (int)pos : queue[pos];
+                    pf = VIRTUAL ? a.w.rec[pos] : qrec[pos];
+                    if (a.u0) pf_u0 = a.u0[pf_id];
+                    pf_valid = true;
+                }
+                cnext += min((int64_t)__popcll(need), avail);
+            }
+        }
+        if (__ballot(active) == 0) {
+            if (__ballot(pf_valid) == 0 && drained && cnext >= cend) break;
             continue;
         }
-        if (!L.active) continue;
 
-        // ---- one step attempt per active lane ------------------------------
-        T ht = L.refine ? L.hh : L.h;
-        bool land = false;
-        if (!L.refine) {
-            if (L.attempts >= a.tol.max_steps) {
-                finish(a, L, UNRESOLVED, L.phi, 0.0);
-                continue;
-            }
-            ++L.attempts;
-            // Shorten a step that would pass the next disk-plane crossing so
-            // that it lands on it exactly.
-            if (L.phi + (double)ht >= L.phik) {
-                ht = T(L.phik - L.phi);
-                land = true;
-            }
-        }
+        // ---- (B) one step evaluation per lane ------------------------------
+        const bool nrm = active && !refine;           // normal trial step
+        const bool capped = nrm && attempts >= max_steps;
+        const T hx = refine ? hh : h;
+        // A trial step that would pass the next disk-plane crossing is
+        // shortened to land on it exactly.
+        const double phx = phi + (double)hx;
+        const bool land = nrm && phx >= phik;
+        const T ht = land ? T(phik - phi) : hx;
         T un, wn, gn, eu, ew;
-        dp45<T>(M3, L.u, L.w, L.g, ht, un, wn, gn, eu, ew);
-        ++L.nsteps;
+        dp45<T>(M3, u, w, g, ht, un, wn, gn, eu, ew);
 
-        if (L.refine) {
-            // Newton on the step length for u(h) = u_sky, from the last
-            // accepted state: h <- h - (u(h) - u_sky) / u'(h).
-            const T dh = (un - usky) / wn;
-            L.hh -= dh;
-            ++L.it;
-            if (fabs(dh) < ntol || L.it >= 4) finish(a, L, SKY, L.phi + (double)L.hh, 0.0);
-            continue;
+        // Error test: accept iff |e_i| <= atol + rtol max(|y_i|, |y_new_i|)
+        // for both components (exact comparison); the ratio for the step-size
+        // proposal needs one reciprocal.
+        const T su = fma(rtol, fmax(fabs(u), fabs(un)), atol);
+        const T sw = fma(rtol, fmax(fabs(w), fabs(wn)), atol);
+        const bool fits = fabs(eu) <= su && fabs(ew) <= sw;
+        const float fsu = (float)su, fsw = (float)sw;
+        const float err = fmaxf((float)fabs(eu) * fsw, (float)fabs(ew) * fsu) *
+                          __builtin_amdgcn_rcpf(fsu * fsw);
+        const float fac = step_factor(err);
+        const float f_acc = fminf(rej ? 1.0f : 5.0f, fmaxf(0.2f, fac));
+        const float f_rej = fmaxf(0.2f, fac);
+        const bool go = nrm && !capped;               // a trial step was taken
+        const bool acc = go && fits;
+
+        // Events of an accepted step, in order: disk, horizon, sky sphere.
+        const double phin = land ? phik : phx;
+        const bool disk_hit = acc && land && un >= urout && un <= urin;
+        const bool capture = acc && !disk_hit && twoM > 0.0 && twoM * (double)un >= 1.0;
+        const bool skyx = acc && !disk_hit && !capture && un <= usky && wn < T(0);
+        const bool advance = acc && !disk_hit && !capture && !skyx;
+        // Newton on the step length for u(h) = u_sky, redoing the step from
+        // the last accepted state: h <- h - (u(h) - u_sky) / u'(h).  The
+        // accepted crossing step gives the first update; each refinement
+        // step gives one more (at most four updates).
+        const bool newton = (active && refine) || skyx;
+        const T dh = (un - usky) * recip(wn);
+        const T hh_new = ht - dh;
+        const int it_new = refine ? it + 1 : 1;
+        const bool sky_done = newton && (fabs(dh) < ntol || it_new >= 4);
+        const bool over = advance && phin > max_phi;
+
+        // State updates.
+        if (go) {
+            ++attempts;
+            h = fmin(acc ? (land ? h : ht * T(f_acc)) : ht * T(f_rej), hmax);
+            rej = !acc;
+        }
+        if (active && !capped) ++nsteps;
+        if (acc && land && !disk_hit) phik += kPi;
+        if (advance) {
+            u = un;
+            w = wn;
+            g = gn;
+            phi = phin;
+        }
+        if (newton) {
+            hh = hh_new;
+            it = it_new;
+            refine = !sky_done;
         }
 
-        const T su = fma(rtol, fmax(fabs(L.u), fabs(un)), atol);
-        const T sw = fma(rtol, fmax(fabs(L.w), fabs(wn)), atol);
-        const bool acc = fabs(eu) <= su && fabs(ew) <= sw;
-        const float err = fmaxf((float)fabs(eu) * __builtin_amdgcn_rcpf((float)su),
-                                (float)fabs(ew) * __builtin_amdgcn_rcpf((float)sw));
-        if (!acc) {
-            L.h = ht * T(fmaxf(0.2f, step_factor(err)));
-            L.rej = true;
-            continue;
+        // A finished ray stores its result record.
+        if (capped || disk_hit || capture || sky_done || over) {
+            const uint8_t cls = (capped || over) ? UNRESOLVED
+                                : disk_hit       ? DISK
+                                : capture        ? CAPTURED
+                                                 : SKY;
+            const double pe = sky_done ? phi + (double)hh_new : (capped ? phi : phin);
+            const double rh = disk_hit ? 1.0 / (double)un : 0.0;
+            a.w.res[id] = make_double2(pe, rh);
+            a.w.clst[id] = (int32_t)cls | (nsteps << 3);
+            active = false;
         }
-        const double phin = land ? L.phik : L.phi + (double)ht;
-        if (!land) {
-            float fac = fminf(5.0f, fmaxf(0.2f, step_factor(err)));
-            if (L.rej) fac = fminf(fac, 1.0f);
-            L.h = ht * T(fac);
-        }
-        L.h = fmin(L.h, hmax);
-        L.rej = false;
-
-        // Events, in order: disk crossing, horizon, sky sphere, sweep cap.
-        if (land) {
-            const double r = 1.0 / (double)un;
-            if (r >= rin && r <= rout) {
-                finish(a, L, DISK, phin, r);
-                continue;
-            }
-            L.phik += kPi;
-        }
-        if (twoM > 0.0 && twoM * (double)un >= 1.0) {
-            finish(a, L, CAPTURED, phin, 0.0);
-            continue;
-        }
-        if (un <= usky && wn < T(0)) {
-            const T dh = (un - usky) / wn;
-            L.hh = ht - dh;
-            if (fabs(dh) < ntol) {
-                finish(a, L, SKY, L.phi + (double)L.hh, 0.0);
-            } else {
-                L.refine = true;  // keep the accepted-from state as the base
-                L.it = 1;
-            }
-            continue;
-        }
-        L.u = un;
-        L.w = wn;
-        L.g = gn;
-        L.phi = phin;
-        if (L.phi > a.tol.max_phi) finish(a, L, UNRESOLVED, L.phi, 0.0);
     }
 }
 
 // FP64 mode: one pass over all rays tagged FP64.
 __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
-    run_queue<double, true>(a, nullptr, a.n, &a.w.ctr[2], PATH_FP64, a.tol.rtol64, a.tol.atol64,
-                            a.tol.newton64);
+    run_queue<double, true>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices, a.tol.rtol64,
+                            a.tol.atol64, a.tol.newton64);
 }
 
-// FP32 mode: wavefronts first drain the (small) FP64 band queue, then the
-// FP32 rays, in one launch so the band's long rays overlap the FP32 work.
-__global__ __launch_bounds__(kBlock) void k_integrate_fp32(IntegArgs a) {
-    const int64_t nband = a.w.ctr[0];
-    run_queue<double, false>(a, a.w.q64, nband, &a.w.ctr[1], PATH_FP64, a.tol.rtol64,
-                             a.tol.atol64, a.tol.newton64);
-    run_queue<float, true>(a, nullptr, a.n, &a.w.ctr[2], PATH_FP32, a.tol.rtol32, a.tol.atol32,
-                           a.tol.newton32);
+// FP32 mode.  The first `band_blocks` blocks first drain the FP64 queue of
+// the critical band, then join the FP32 rays.  Band rays are few but long (up
+// to a few hundred FP64 steps) and latency-bound; their waves start with the
+// launch and run at raised issue priority, so the FP32 waves sharing their
+// SIMDs fill the gaps and the band ends inside the FP32 work instead of
+// trailing it.  The kernel is held to 64 VGPRs (8 waves per SIMD for the FP32
+// rays); the FP64 code spills a few registers, which only band waves pay.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
+k_integrate_fp32(IntegArgs a, int band_blocks) {
+    if ((int)blockIdx.x < band_blocks) {
+        __builtin_amdgcn_s_setprio(3);
+        IntegArgs ab = a;
+        ab.chunk = 64;
+        run_queue<double, false>(ab, a.w.q64, a.w.q64rec, a.w.ctr[kCtrBandSize], &a.w.ctr[kCtrBand],
+                                 1, a.tol.rtol64, a.tol.atol64, a.tol.newton64);
+        __builtin_amdgcn_s_setprio(0);
+    }
+    run_queue<float, true>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices, a.tol.rtol32,
+                           a.tol.atol32, a.tol.newton32);
 }
 
 // ---------------------------------------------------------------------------
@@ -443,9 +493,11 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
     double o[3], dv[3];
     source_ray(src, i, o, dv);
     const Basis B = plane_basis(o, dv, sc.M, sc.r_sky);
-    const uint8_t cls = w.cls[i];
-    const double phi = w.phi_end[i];
-    const double r_hit = w.r_hit[i];
+    const int32_t cs = w.clst[i];
+    const uint8_t cls = (uint8_t)(cs & 7);
+    const double2 rr = w.res[i];
+    const double phi = rr.x;
+    const double r_hit = rr.y;
     double sphi, cphi;
     sincos(phi, &sphi, &cphi);
     double s[3];
@@ -472,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
     if (out.cls) out.cls[i] = cls;
     if (out.phi_end) out.phi_end[i] = phi;
     if (out.r_hit) out.r_hit[i] = r_hit;
-    if (out.steps) out.steps[i] = w.steps[i];
+    if (out.steps) out.steps[i] = cs >> 3;
     if (out.path) out.path[i] = w.path[i];
     if (out.exit_dir) {
 #pragma unroll
@@ -511,10 +563,31 @@ hipError_t launch_setup(const Source& src, const DevScene& sc, const DevRoute& r
     return hipGetLastError();
 }
 
+// Resident blocks per CU of a kernel (queried once).
+template <typename K>
+static int blocks_per_cu(K kernel, int* cache) {
+    if (*cache == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess ||
+            nb < 1)
+            nb = 1;
+        *cache = nb;
+    }
+    return *cache;
+}
+
+static unsigned persistent_grid(int64_t n, int cus, int per_cu, int grid_blocks) {
+    int64_t g = grid_blocks > 0 ? grid_blocks : (int64_t)cus * per_cu;
+    const int64_t need = (n + kBlock - 1) / kBlock;
+    if (g > need) g = need;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
 hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, const DevScene& sc,
-                            const DevTol& tol, int precision, const Work& w, int grid_blocks,
-                            int chunk, hipStream_t s) {
+                            const DevTol& tol, int precision, const Work& w, int cus,
+                            int grid_blocks, int chunk, hipStream_t s) {
     if (n == 0) return hipSuccess;
+    static int occ64 = 0, occ32 = 0;
     IntegArgs a;
     a.n = n;
     a.u0 = explicit_u0 ? w.u0 : nullptr;
@@ -523,10 +596,14 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
     a.tol = tol;
     a.w = w;
     a.chunk = chunk;
-    if (precision == 1)
-        k_integrate_fp32<<<grid_blocks, kBlock, 0, s>>>(a);
-    else
-        k_integrate_fp64<<<grid_blocks, kBlock, 0, s>>>(a);
+    if (precision != 1) {
+        const unsigned g = persistent_grid(n, cus, blocks_per_cu(k_integrate_fp64, &occ64), grid_blocks);
+        k_integrate_fp64<<<g, kBlock, 0, s>>>(a);
+    } else {
+        const unsigned g = persistent_grid(n, cus, blocks_per_cu(k_integrate_fp32, &occ32), grid_blocks);
+        const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
+        k_integrate_fp32<<<g, kBlock, 0, s>>>(a, band_blocks);
+    }
     return hipGetLastError();
 }
 
