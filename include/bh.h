@@ -104,6 +104,8 @@ typedef struct {
                                 effective potential peaks at b = 3 sqrt(3) M)          */
     int    grid_blocks;      /* persistent integrator grid, 256-thread blocks; 0 = auto */
     int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto  */
+    const struct bh_surrogate* surrogate; /* FP32 renders only: route eligible rays to this
+                                trained network (NULL = off; see bh_surrogate_*)     */
 } bh_options;
 
 /* Optional per-ray outputs (device arrays of length n, any may be NULL).
@@ -150,6 +152,66 @@ bh_status bh_reserve(int64_t n);
  * counts[0..3] = {set-up only, FP64 integrator, FP32 integrator, surrogate}.
  * Synchronises `stream`. */
 bh_status bh_last_counts(int64_t counts[4], void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned surrogate of the sweep (an extension of the paper's method): an MLP
+ * 2 -> 128 -> 128 -> 128 -> 2 (ReLU) maps (b/M, r0/M) of an ingoing ray to the
+ * exit azimuth on the sky sphere at r_sky = 1000 M (as a residual over the
+ * first-order weak-field sweep, scaled by 12 (M/b)^2) and a capture logit.
+ * BF16 weights and activations on the matrix cores, FP32 accumulation and FP32
+ * master weights with Adam.  Labels come from the FP64 integrator.  A trust
+ * map over (ln(b - 3 sqrt(3) M), r0) bins, built from the integrator's labels,
+ * gates which rays a render may hand to the network; outside the band, with
+ * the periapsis beyond the disk, in a trusted bin.  Rays whose capture logit
+ * disagrees with b > 3 sqrt(3) M go back to the integrator.
+ *
+ * Parameters are one float vector of 33666 values in the order
+ * W1[2][128] b1[128] W2[128][128] b2 W3[128][128] b3 W4[128][2] b4[2]
+ * (row-major, layer input index first).  All array arguments are device
+ * pointers unless named host_*; sizes are element counts.
+ * ------------------------------------------------------------------------- */
+typedef struct bh_surrogate bh_surrogate;
+typedef struct { float lr, beta1, beta2, eps; } bh_adam;
+
+/* Creates a network from host params (count must be 33666); training batches
+ * are multiples of 32 up to max_batch.  Synchronous. */
+bh_status bh_surrogate_create(const float* host_params, int64_t count, int64_t max_batch,
+                              bh_surrogate** out);
+bh_status bh_surrogate_destroy(bh_surrogate* s);
+/* Copies {0 params, 1 last gradient, 2 Adam m, 3 Adam v} to host (33666
+ * floats).  Synchronous. */
+bh_status bh_surrogate_params(const bh_surrogate* s, int which, float* host_out, int64_t count);
+/* Replaces params (and Adam state if m, v are non-NULL; step = Adam step
+ * count) from host arrays, e.g. to resume from a checkpoint.  Synchronous. */
+bh_status bh_surrogate_set_params(bh_surrogate* s, const float* host_params, const float* host_m,
+                                  const float* host_v, int step);
+/* One training step on n samples (b, r0 in units of M; phi_exit = labelled
+ * exit azimuth, NaN unless the ray escaped; captured = 0/1): forward, loss
+ * (1/n) sum [escaped (y0 - t)^2 + 0.1 BCE(y1, captured)], backward and, if
+ * hp->lr > 0, one Adam step.  loss (device float, may be NULL) receives the
+ * loss before the step.  n is a multiple of 32 up to max_batch. */
+bh_status bh_surrogate_train_step(bh_surrogate* s, const double* b, const double* r0,
+                                  const double* phi_exit, const uint8_t* captured, int64_t n,
+                                  const bh_adam* hp, float* loss, void* stream);
+/* Network outputs y (n x 2 floats) and/or predicted exit azimuth (n doubles)
+ * for samples (b, r0); either output may be NULL. */
+bh_status bh_surrogate_infer(const bh_surrogate* s, const double* b, const double* r0, int64_t n,
+                             float* y, double* phi_pred, void* stream);
+/* Labels by FP64 integration (rtol 1e-10, r_sky = 1000, M = 1) of the ingoing
+ * ray from (r0, 0, 0) with impact parameter b: phi_exit (NaN unless it
+ * escaped) and captured (0/1).  Pairs no ray from r0 can have give NaN, 0. */
+bh_status bh_surrogate_labels(bh_surrogate* s, const double* b, const double* r0, int64_t n,
+                              double* phi_exit, uint8_t* captured, void* stream);
+/* Builds the trust map from n validation samples with labelled phi_true: a
+ * bin is trusted if it holds >= min_count escaping samples whose predicted
+ * exit azimuth is within max_err (rad) and whose capture logit is negative.
+ * y_scratch (n x 2 floats) and phi_scratch (n doubles) are caller scratch. */
+bh_status bh_surrogate_build_trust(bh_surrogate* s, const double* b, const double* r0,
+                                   const double* phi_true, int64_t n, float max_err, int min_count,
+                                   float* y_scratch, double* phi_scratch, void* stream);
+/* Copies the trust map (256 x 64 bytes, 1 = trusted) to / from the host. */
+bh_status bh_surrogate_trust(const bh_surrogate* s, uint8_t* host_map, int64_t count);
+bh_status bh_surrogate_set_trust(bh_surrogate* s, const uint8_t* host_map, int64_t count);
 
 /* Kernel timing for benchmarks.  While enabled, every kernel launch of the
  * library is bracketed by a pair of hipEvents recorded on its launch stream.

@@ -14,7 +14,10 @@ and initial conditions give the labels, see bh_ref.c):
   - exit azimuth  phi_exit = sweep1(b, r0, R) + S(b) y0, with sweep1 the
     first-order weak-field sweep and S(b) = 12 (M/b)^2 its residual scale;
   - loss      L = (1/B) sum_i [ e_i (y0_i - t_i)^2 + 0.1 BCE(y1_i, c_i) ],
-              t = (phi_exit_true - sweep1) / S, e_i = 1 for escaping rays,
+              t = (phi_exit_true - sweep1) / S, e_i = 1 for escaping rays with
+              b >= 10 M (the regression domain: closer to the critical value the
+              residual is too steep for bf16 activations to meet 1e-4 rad, and
+              the trust map keeps such rays on the integrator anyway),
               c_i = 1 for captured rays;
   - Adam (Kingma & Ba 2015) on FP32 master weights; the network runs on the
     bf16-rounded copy.
@@ -59,6 +62,14 @@ def sweep_first_order(b, r0, r_sky=R_SKY):
         return np.arcsin(np.clip(b / r - (2.0 - b * b / (r * r)) / b, -1.0, 1.0))
 
     return math.pi - a(r_sky) - a(np.asarray(r0, np.float64))
+
+
+REGRESSION_B_MIN = 10.0
+
+
+def regression_mask(b, phi_exit):
+    """Samples that carry the squared-error term: escaped, b >= 10 M."""
+    return np.isfinite(np.asarray(phi_exit, np.float64)) & (np.asarray(b) >= REGRESSION_B_MIN)
 
 
 def targets(b, r0, phi_exit):

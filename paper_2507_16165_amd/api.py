@@ -39,7 +39,12 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("atol", C.c_double),
                 ("rtol_fp32", C.c_double), ("band_halfwidth", C.c_double), ("h0", C.c_double),
                 ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
-                ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int)]
+                ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
+                ("surrogate", C.c_void_p)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class RayOut(C.Structure):
@@ -76,6 +81,23 @@ def lib():
     L.bh_timing_enable.restype = st
     L.bh_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.bh_timing_read.restype = st
+    vp, i64 = C.c_void_p, C.c_int64
+    sigs = {
+        "bh_surrogate_create": [vp, i64, i64, C.POINTER(C.c_void_p)],
+        "bh_surrogate_destroy": [vp],
+        "bh_surrogate_params": [vp, C.c_int, vp, i64],
+        "bh_surrogate_set_params": [vp, vp, vp, vp, C.c_int],
+        "bh_surrogate_train_step": [vp, vp, vp, vp, vp, i64, C.POINTER(Adam), vp, vp],
+        "bh_surrogate_infer": [vp, vp, vp, i64, vp, vp, vp],
+        "bh_surrogate_labels": [vp, vp, vp, i64, vp, vp, vp],
+        "bh_surrogate_build_trust": [vp, vp, vp, vp, i64, C.c_float, C.c_int, vp, vp, vp],
+        "bh_surrogate_trust": [vp, vp, i64],
+        "bh_surrogate_set_trust": [vp, vp, i64],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = st
     L.bh_shutdown.argtypes = []
     L.bh_shutdown.restype = st
     L.bh_last_error.argtypes = []
@@ -195,3 +217,93 @@ def timing_read() -> dict:
 
 def shutdown() -> None:
     check(lib().bh_shutdown())
+
+
+# -- surrogate -------------------------------------------------------------
+
+NPARAM = 33666
+TRUST_SHAPE = (256, 64)
+
+
+class Surrogate:
+    """Owner of a bh_surrogate handle (the network, its Adam state, its
+    training scratch and trust map live on the device)."""
+
+    def __init__(self, params, max_batch: int = 4096):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        h = C.c_void_p()
+        check(lib().bh_surrogate_create(p.ctypes.data, p.size, int(max_batch), C.byref(h)))
+        self.handle = h
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if self.handle:
+            check(lib().bh_surrogate_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get(self, which: int = 0):
+        """0 params, 1 last gradient, 2 Adam m, 3 Adam v (host float32)."""
+        import numpy as np
+        out = np.empty(NPARAM, np.float32)
+        check(lib().bh_surrogate_params(self.handle, which, out.ctypes.data, NPARAM))
+        return out
+
+    def set(self, params, m=None, v=None, step: int = 0):
+        import numpy as np
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (params, m, v)]
+        ptrs = [None if a is None else a.ctypes.data for a in arrs]
+        check(lib().bh_surrogate_set_params(self.handle, ptrs[0], ptrs[1], ptrs[2], int(step)))
+
+    def train_step(self, b, r0, phi, cap, lr, loss=None, beta1=0.9, beta2=0.999, eps=1e-8,
+                   stream=None):
+        hp = Adam(lr, beta1, beta2, eps)
+        check(lib().bh_surrogate_train_step(self.handle, b.data_ptr(), r0.data_ptr(), phi.data_ptr(),
+                                            cap.data_ptr(), b.numel(), C.byref(hp),
+                                            loss.data_ptr() if loss is not None else None,
+                                            _stream(stream)))
+
+    def infer(self, b, r0, stream=None):
+        import torch
+        n = b.numel()
+        y = torch.empty((n, 2), dtype=torch.float32, device=b.device)
+        phi = torch.empty(n, dtype=torch.float64, device=b.device)
+        check(lib().bh_surrogate_infer(self.handle, b.data_ptr(), r0.data_ptr(), n, y.data_ptr(),
+                                       phi.data_ptr(), _stream(stream)))
+        return y, phi
+
+    def labels(self, b, r0, stream=None):
+        import torch
+        n = b.numel()
+        phi = torch.empty(n, dtype=torch.float64, device=b.device)
+        cap = torch.empty(n, dtype=torch.uint8, device=b.device)
+        check(lib().bh_surrogate_labels(self.handle, b.data_ptr(), r0.data_ptr(), n, phi.data_ptr(),
+                                        cap.data_ptr(), _stream(stream)))
+        return phi, cap
+
+    def build_trust(self, b, r0, phi, max_err: float, min_count: int = 3, stream=None):
+        import torch
+        n = b.numel()
+        y = torch.empty((n, 2), dtype=torch.float32, device=b.device)
+        pp = torch.empty(n, dtype=torch.float64, device=b.device)
+        check(lib().bh_surrogate_build_trust(self.handle, b.data_ptr(), r0.data_ptr(), phi.data_ptr(),
+                                             n, float(max_err), int(min_count), y.data_ptr(),
+                                             pp.data_ptr(), _stream(stream)))
+
+    def trust(self):
+        import numpy as np
+        m = np.empty(TRUST_SHAPE, np.uint8)
+        check(lib().bh_surrogate_trust(self.handle, m.ctypes.data, m.size))
+        return m
+
+    def set_trust(self, m):
+        import numpy as np
+        m = np.ascontiguousarray(m, np.uint8)
+        assert m.shape == TRUST_SHAPE
+        check(lib().bh_surrogate_set_trust(self.handle, m.ctypes.data, m.size))

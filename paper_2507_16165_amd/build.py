@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libbh.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["bh_kernels.hip", "bh_abi.cpp"]
+SOURCES = ["bh_kernels.hip", "bh_surrogate.hip", "bh_abi.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC,

@@ -12,7 +12,7 @@
 
 #include "bh_internal.h"
 
-namespace {
+namespace bh {
 
 thread_local char g_err[512] = "";
 
@@ -27,6 +27,13 @@ bh_status fail(bh_status st, const char* fmt, ...) {
 bh_status hip_fail(hipError_t e, const char* what) {
     return fail(BH_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace bh
+
+namespace {
+
+using bh::fail;
+using bh::hip_fail;
 
 constexpr double kPi = 3.14159265358979323846;
 
@@ -102,7 +109,7 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
         const size_t sz16 = align256((size_t)cap * 16), sz8 = align256((size_t)cap * 8),
                      sz4 = align256((size_t)cap * 4), sz1 = align256((size_t)cap);
         const size_t szc = align256(sizeof(int32_t) * bh::kCtrInts);
-        const size_t total = 3 * sz16 + sz8 + 2 * sz4 + sz1 + szc + 256;
+        const size_t total = 4 * sz16 + sz8 + 2 * sz4 + sz1 + szc + 256;
         if (ws.base) {
             e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -122,6 +129,7 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
         ws.w.rec = (double2*)c; c += sz16;
         ws.w.res = (double2*)c; c += sz16;
         ws.w.q64rec = (double2*)c; c += sz16;
+        ws.w.sur = (double2*)c; c += sz16;
         ws.w.u0 = (double*)c; c += sz8;
         ws.w.clst = (int32_t*)c; c += sz4;
         ws.w.q64 = (int32_t*)c; c += sz4;
@@ -202,6 +210,8 @@ bh::DevRoute dev_route(const bh_options* o, const bh_scene* sc) {
     r.precision = o->precision;
     r.analytic_capture = o->analytic_capture ? 1 : 0;
     r.band = o->band_halfwidth * sc->M;
+    r.trust = nullptr;
+    r.r0m = 0.0f;
     return r;
 }
 
@@ -229,7 +239,16 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     if (st != BH_OK) return st;
     const bh::DevScene sc = dev_scene(scene);
     const bh::DevTol tol = dev_tol(opt, scene);
-    const bh::DevRoute rt = dev_route(opt, scene);
+    bh::DevRoute rt = dev_route(opt, scene);
+    // The surrogate serves FP32 renders of scenes with the sky at 1000 M (the
+    // radius it was trained for).
+    const void* sur_pack = nullptr;
+    if (opt->surrogate && !explicit_u0 && opt->precision == BH_FP32 && scene->M > 0.0 &&
+        fabs(scene->r_sky / scene->M - 1000.0) < 1e-9) {
+        rt.trust = bh::surrogate_trust(opt->surrogate);
+        rt.r0m = (float)(1.0 / (u0_uniform * scene->M));
+        sur_pack = rt.trust ? bh::surrogate_pack(opt->surrogate) : nullptr;
+    }
     bh::Work w = ws->w;
     if (!explicit_u0) w.u0 = nullptr;
     hipError_t e = bh::launch_reset(w.ctr, stream);
@@ -238,6 +257,13 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     e = bh::launch_setup(src, sc, rt, w, out ? out->b : nullptr, stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "setup");
+    if (sur_pack) {
+        t = timing_begin(3, stream);
+        e = bh::launch_surrogate_render(src.n, w, sur_pack, scene->M, 1.0 / u0_uniform, ws->cus,
+                                        stream);
+        timing_end(t, stream);
+        if (e != hipSuccess) return hip_fail(e, "surrogate");
+    }
     t = timing_begin(1, stream);
     e = bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w, ws->cus,
                              opt->grid_blocks, auto_chunk(opt), stream);
@@ -403,6 +429,6 @@ bh_status bh_shutdown(void) {
     return BH_OK;
 }
 
-const char* bh_last_error(void) { return g_err; }
+const char* bh_last_error(void) { return bh::g_err; }
 
 }  // extern "C"

@@ -5,10 +5,45 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bh.h"
+
 namespace bh {
+
+// Error reporting shared by the ABI entry points (bh_abi.cpp).
+bh_status fail(bh_status st, const char* fmt, ...);
+bh_status hip_fail(hipError_t e, const char* what);
 
 constexpr int kBlock = 256;   // threads per block for every kernel
 constexpr int kWave = 64;     // CDNA wavefront
+
+// Per-ray path tags (bh_ray_out.path) and end classes.
+enum : uint8_t { SKY = 0, CAPTURED = 1, DISK = 2, UNRESOLVED = 3, INVALID = 4 };
+enum : uint8_t { PATH_NONE = 0, PATH_FP64 = 1, PATH_FP32 = 2, PATH_SUR = 3 };
+
+// Surrogate trust map: 256 bins of ln(b - b_c) x 64 bins of r0 (see trust_bin).
+constexpr int kTrustB = 256, kTrustR = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int rank_in(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Trust-map bin of (b/M, r0/M) on the escape side of the band: 256 bins of
+// ln(b - b_c) over [ln 0.05, ln 995] times 64 bins of r0 over [10, 200]; -1
+// outside.  Evaluated in FP32 on the device both when the map is built and
+// when rays are routed, so both see the same bins.
+__device__ __forceinline__ int trust_bin(float bm, float r0m) {
+    const float d = bm - 5.19615242270663188f;
+    if (!(d > 0.05f)) return -1;
+    const float lo = -2.99573227f, hi = 6.90274738f;  // ln 0.05, ln 995
+    const float x = (__logf(d) - lo) * (256.0f / (hi - lo));
+    const float y = (r0m - 10.0f) * (64.0f / 190.0f);
+    if (!(x >= 0.0f && x < 256.0f && y >= 0.0f && y < 64.0f)) return -1;
+    return (int)x * kTrustR + (int)y;
+}
 
 // Scene constants in the form the kernels use.
 struct DevScene {
@@ -43,6 +78,8 @@ struct DevRoute {
     int precision;            // BH_FP64 / BH_FP32
     int analytic_capture;
     double band;              // half-width of the critical band, absolute units
+    const uint8_t* trust;     // surrogate trust map, or NULL: no surrogate routing
+    float r0m;                // camera distance / M (surrogate routing only)
 };
 
 // Per-ray workspace (structure of arrays, capacity >= rays of the call).
@@ -50,6 +87,7 @@ struct Work {
     double* u0;               // 1/|origin| per ray (explicit-ray mode only)
     double2* rec;             // start record {w0, phi1}; w0 = NaN: not in the main queue
     double2* res;             // result record {phi_end, r_hit}
+    double2* sur;             // surrogate rays: {b, w0}
     int32_t* clst;            // class | (step evaluations << 3)
     uint8_t* path;
     int32_t* q64;             // FP64 band queue (FP32 mode): ray indices ...
@@ -64,7 +102,8 @@ constexpr int kSlices = 8;                              // main-queue slices
 constexpr int kCtrBandSize = 0;                         // FP64 band queue length
 constexpr int kCtrBand = kCtrStride;                    // band queue head
 constexpr int kCtrMain = 2 * kCtrStride;                // kSlices main-queue heads
-constexpr int kCtrInts = kCtrMain + kSlices * kCtrStride;
+constexpr int kCtrSur = kCtrMain + kSlices * kCtrStride; // kSlices surrogate-scan heads
+constexpr int kCtrInts = kCtrSur + kSlices * kCtrStride;
 
 // Optional caller-owned outputs (mirrors bh_ray_out).
 struct Out {
@@ -94,6 +133,12 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
                             int grid_blocks, int chunk, hipStream_t s);
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
                         const Out& out, hipStream_t s);
+// Surrogate (bh_surrogate.hip): the device trust map (NULL until built) and
+// inference pack of a handle, and the render-path kernel over PATH_SUR rays.
+const uint8_t* surrogate_trust(const bh_surrogate* s);
+const void* surrogate_pack(const bh_surrogate* s);
+hipError_t launch_surrogate_render(int64_t n, const Work& w, const void* pack, double M,
+                                   double r_cam, int cus, hipStream_t s);
 hipError_t launch_count_paths(int64_t n, const Work& w, unsigned long long* counts, hipStream_t s);
 
 }  // namespace bh

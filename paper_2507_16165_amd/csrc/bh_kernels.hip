@@ -19,21 +19,9 @@
 
 namespace bh {
 
-enum : uint8_t { SKY = 0, CAPTURED = 1, DISK = 2, UNRESOLVED = 3, INVALID = 4 };
-enum : uint8_t { PATH_NONE = 0, PATH_FP64 = 1, PATH_FP32 = 2, PATH_SUR = 3 };
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kBcrit = 5.19615242270663188058;  // 3 sqrt(3)
-
-// ---------------------------------------------------------------------------
-// Wave helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
-
-__device__ __forceinline__ int rank_in(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 // ---------------------------------------------------------------------------
 // Geometry shared by set-up and shading (identical code, so both stages see
@@ -149,8 +137,20 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
             const double bc = kBcrit * sc.M;
             if (w.u0) w.u0[i] = u0;
             phi1 = sc.has_disk ? first_crossing(B.e1[2], B.e2[2]) : __builtin_inf();
+            // Surrogate: ingoing rays above the band whose periapsis lies
+            // outside the disk (u_out^2 - 2 M u_out^3 > 1/b^2: the ray turns
+            // before reaching r_out), in a bin the trust map accepts.
+            bool sur = false;
+            if (rt.trust && B.c < 0.0 && b > bc + rt.band &&
+                (!sc.has_disk || sc.urout * sc.urout * (1.0 - 2.0 * sc.M * sc.urout) > E0)) {
+                const int bin = trust_bin((float)(b / sc.M), rt.r0m);
+                sur = bin >= 0 && rt.trust[bin] != 0;
+            }
             if (rt.analytic_capture && !sc.has_disk && B.c < 0.0 && b < bc - rt.band) {
                 cls = CAPTURED;  // below the potential peak: falls in, no disk to hit
+            } else if (sur) {
+                path = PATH_SUR;
+                w.sur[i] = make_double2(b, w0);
             } else if (rt.precision == 1 && fabs(b - bc) < rt.band) {
                 path = PATH_FP64;
                 to_q64 = true;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
         w.path[i] = path;
         // The main queue is the index range itself; its record marks rays
         // that belong to another path (band, set-up only) with w0 = NaN.
-        const bool main = path != PATH_NONE && !to_q64;
+        const bool main = path != PATH_NONE && path != PATH_SUR && !to_q64;
         w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
         if (path == PATH_NONE) {
             w.res[i] = make_double2(phi_end, 0.0);

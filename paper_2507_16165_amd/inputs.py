@@ -129,12 +129,17 @@ def random_rays(n: int, seed: int, r_min: float, r_max: float, aim_scale: float 
 
 
 def surrogate_samples(n: int, seed: int, b_lo: float, b_hi: float, r0_lo: float = 10.0,
-                      r0_hi: float = 200.0):
+                      r0_hi: float = 200.0, max_b_over_r0: float | None = 0.85):
     """(b/M, r0/M) pairs: b log-uniform in [b_lo, b_hi], r0 uniform in
-    [r0_lo, r0_hi].  Callers reject pairs that no ray from r0 can have."""
+    [r0_lo, r0_hi], keeping b <= max_b_over_r0 * r0 (a camera with a 60-degree
+    vertical field of view at 16:9 sees rays up to b = 0.76 r0; nearer b = r0
+    the ray starts at its periapsis).  Returns at most n pairs."""
     rng = np.random.default_rng(seed)
     b = np.exp(rng.uniform(np.log(b_lo), np.log(b_hi), n))
     r0 = rng.uniform(r0_lo, r0_hi, n)
+    if max_b_over_r0 is not None:
+        keep = b <= max_b_over_r0 * r0
+        b, r0 = b[keep], r0[keep]
     return b, r0
 
 

@@ -1,0 +1,225 @@
+"""Surrogate network on the GPU (through the C ABI) against the FP64 oracle:
+inference, gradients and Adam on identical (bf16-rounded) weights and batch,
+labels against the oracle tracer, a short training run with its trust map,
+renders that route rays to the network, and the measured gain."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as R
+from paper_2507_16165_amd import inputs
+from parity import B_CRIT, compare
+
+pytestmark = pytest.mark.gpu
+
+OFFS = [0, 256, 384, 16768, 16896, 33280, 33408, 33664, 33666]
+SHAPES = [(2, 128), (128,), (128, 128), (128,), (128, 128), (128,), (128, 2), (2,)]
+
+
+def split(p):
+    return [p[OFFS[i]:OFFS[i + 1]].reshape(SHAPES[i]) for i in range(8)]
+
+
+@pytest.fixture(scope="module")
+def bh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2507_16165_amd import api
+    api.lib()
+    return api
+
+
+@pytest.fixture(scope="module")
+def rand_params():
+    from paper_2507_16165_amd import surrogate as S
+    p = S.init_params(1)
+    rng = np.random.default_rng(7)
+    for a, b in ((256, 384), (16768, 16896), (33280, 33408), (33664, 33666)):
+        p[a:b] = rng.normal(scale=0.1, size=b - a)
+    return p
+
+
+def _batch(n, seed):
+    rng = np.random.default_rng(seed)
+    b = np.where(rng.uniform(size=n) < 0.8, np.exp(rng.uniform(np.log(5.3), np.log(150), n)),
+                 rng.uniform(0, 5.1, n))
+    r0 = rng.uniform(160, 200, n)
+    return b, r0
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def test_inference_matches_oracle_forward(bh, rand_params):
+    import torch
+    sur = bh.Surrogate(rand_params, max_batch=1024)
+    b, r0 = _batch(1000, 1)  # not a multiple of 32: ragged last tile
+    y, phi = sur.infer(_t(b), _t(r0))
+    torch.cuda.synchronize()
+    yr, _ = R.forward([R.bf16_round(x) for x in split(rand_params)], R.features(b, r0))
+    y = y.cpu().numpy()
+    # bf16 activations: ~2^-9 relative per layer
+    assert np.abs(y - yr).max() <= 2e-2 * np.abs(yr).max()
+    # the exit azimuth is the oracle's baseline plus the scaled output (FP64)
+    np.testing.assert_allclose(phi.cpu().numpy(), R.predict_exit(b, r0, y[:, 0]), atol=1e-12)
+    sur.close()
+
+
+def test_gradients_and_adam_match_oracle(bh, rand_params):
+    import torch
+    sur = bh.Surrogate(rand_params, max_batch=1024)
+    b, r0 = _batch(512, 2)
+    rng = np.random.default_rng(3)
+    esc = b > B_CRIT
+    phi = np.where(esc, R.predict_exit(b, r0, rng.normal(size=b.size)), np.nan)
+    cap = (~esc).astype(np.uint8)
+    loss = torch.zeros(1, device="cuda")
+    sur.train_step(_t(b), _t(r0), _t(phi), _t(cap), 0.0, loss)  # lr = 0: gradient only
+    torch.cuda.synchronize()
+    pr = [R.bf16_round(x) for x in split(rand_params)]
+    y, cache = R.forward(pr, R.features(b, r0))
+    e = R.regression_mask(b, phi).astype(float)
+    L, dy = R.loss_and_dy(y, R.targets(b, r0, phi), e, cap.astype(float))
+    gref = R.backward(pr, cache, dy)
+    assert abs(loss.item() / L - 1.0) < 1e-2
+    for k, (g, gr) in enumerate(zip(split(sur.get(1)), gref)):
+        rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+        assert rel < 4e-2, (k, rel)  # bf16 activations and output gradients
+    np.testing.assert_array_equal(sur.get(0), rand_params)  # lr = 0 left the weights alone
+    # one Adam step, checked against the oracle's update with the GPU's gradient
+    p0 = sur.get(0)
+    sur.train_step(_t(b), _t(r0), _t(phi), _t(cap), 1e-3, loss)
+    p1, g1 = sur.get(0), sur.get(1)
+    z = np.zeros_like(p0)
+    pa, ma, va = R.adam_step([p0], [g1], [z], [z], 1, 1e-3)
+    assert np.abs(p1 - pa[0]).max() < 1e-6
+    np.testing.assert_allclose(sur.get(2), ma[0], rtol=1e-6, atol=1e-12)
+    sur.close()
+
+
+def test_labels_match_oracle_tracer(bh, ref):
+    import torch
+    sur = bh.Surrogate(np.zeros(bh.NPARAM, np.float32), max_batch=32)
+    rng = np.random.default_rng(4)
+    b = np.concatenate([np.exp(rng.uniform(np.log(5.3), np.log(150), 3000)), rng.uniform(0, 5.1, 500),
+                        [250.0]])  # the last pair is infeasible from r0 <= 200
+    r0 = np.concatenate([rng.uniform(160, 200, 3000), rng.uniform(10, 200, 500), [100.0]])
+    phi, cap = sur.labels(_t(b), _t(r0))
+    torch.cuda.synchronize()
+    phi, cap = phi.cpu().numpy(), cap.cpu().numpy()
+    u0 = 1 / r0
+    with np.errstate(invalid="ignore"):
+        sp = u0 / np.sqrt(1 / b**2 + 2 * u0**3)
+        d = np.stack([-np.sqrt(1 - sp**2), sp, 0 * sp], -1)
+    rr = ref.trace_rays(np.stack([r0, 0 * r0, 0 * r0], -1), d, ref.scene(1.0))
+    ok = np.abs(b - B_CRIT) > 0.05
+    np.testing.assert_array_equal((cap == 1)[ok], (rr.cls == ref.CAPTURED)[ok])
+    sky = ok & (rr.cls == ref.SKY)
+    assert np.abs(phi[sky] - rr.phi_end[sky]).max() < 1e-8
+    assert np.isnan(phi[-1]) and cap[-1] == 0
+    sur.close()
+
+
+@pytest.fixture(scope="module")
+def trained(bh):
+    from paper_2507_16165_amd import surrogate as S
+    sur, rep = S.fit(n_escape=1_000_000, n_capture=200_000, n_val=1_000_000, epochs=20,
+                     log=lambda m: print(m, flush=True))
+    print("fit:", rep, flush=True)
+    return sur, rep
+
+
+def test_training_converges_and_trust_map_holds(bh, trained, ref):
+    """Training lowers the loss by 10x; on fresh samples in trusted bins the
+    predicted exit azimuth is within 1e-4 rad of the oracle tracer."""
+    import torch
+    sur, rep = trained
+    assert rep["trusted_bins"] > 200
+    assert rep["val"]["capture_agreement"] > 0.999
+    trust = sur.trust()
+    rng = np.random.default_rng(41)
+    b = np.exp(rng.uniform(np.log(B_CRIT + 0.05), np.log(150), 20000))
+    r0 = rng.uniform(160, 200, 20000)
+    _, phi = sur.infer(_t(b), _t(r0))
+    torch.cuda.synchronize()
+    phi = phi.cpu().numpy()
+    lb = (np.log(b - B_CRIT) - np.log(0.05)) / (np.log(995) - np.log(0.05)) * 256
+    rb = (r0 - 10) / 190 * 64
+    inside = (lb > 0.01) & (lb < 255.99) & (np.abs(lb - np.round(lb)) > 1e-3) & (np.abs(rb - np.round(rb)) > 1e-3)
+    t = np.zeros(b.size, bool)
+    t[inside] = trust[lb[inside].astype(int), rb[inside].astype(int)] == 1
+    assert t.sum() > 1000
+    u0 = 1 / r0[t]
+    sp = u0 / np.sqrt(1 / b[t]**2 + 2 * u0**3)
+    rr = ref.trace_rays(np.stack([r0[t], 0 * u0, 0 * u0], -1),
+                        np.stack([-np.sqrt(1 - sp**2), sp, 0 * sp], -1), ref.scene(1.0))
+    err = np.abs(phi[t] - rr.phi_end)
+    assert err.max() <= 1e-4, err.max()
+
+
+def _render(bh, frame, sur=None):
+    import torch
+    opt = bh.options(precision=bh.FP32)
+    if sur is not None:
+        opt.surrogate = sur.handle
+    rgba, out = bh.render(frame.camera, frame.scene, opt, fields=bh.ALL_FIELDS)
+    torch.cuda.synchronize()
+    return rgba.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("k", [3, 9])
+def test_render_with_surrogate_matches_oracle(bh, trained, ref, k):
+    """4K orbit frames with the surrogate: surrogate-routed rays exist and every
+    ray (surrogate or integrator) meets the FP32 path's bounds on sampled rows."""
+    from test_gpu_parity import oracle_rows
+    sur, _ = trained
+    f = inputs.orbit_4k()[k]
+    rgba, out = _render(bh, f, sur)
+    n_sur = int((out["path"] == bh.PATH_SURROGATE).sum())
+    print(f"frame {k}: r/M = {f.camera.r / f.scene.M:.1f}, surrogate rays {n_sur}", flush=True)
+    H = f.camera.height
+    rows = sorted(set(np.linspace(0, H - 1, 9).astype(int)))
+    _, r_rays, mask = oracle_rows(ref, f, rows)
+    s = compare(r_rays, out, f.scene, "fp32", mask=mask)
+    on = mask & (out["path"] == bh.PATH_SURROGATE)
+    if on.any():
+        from parity import angle_between
+        assert angle_between(r_rays.exit_dir[on], out["exit_dir"][on]).max() <= 1e-4
+    assert s["max_angle"] <= 1e-4
+
+
+def test_surrogate_gain(bh, trained):
+    """What the trained network gains over the integrator alone on the 16-frame
+    4K orbit (FP32 + band both ways): prints the measured ratio of throughputs
+    (it may be below 1) and checks the share of rays the network served."""
+    import torch
+    sur, _ = trained
+    frames = inputs.orbit_4k()
+    buf = torch.empty((2160, 3840, 4), dtype=torch.float32, device="cuda")
+    res = {}
+    for name, handle in (("integrator", None), ("surrogate", sur.handle)):
+        opt = bh.options(precision=bh.FP32)
+        opt.surrogate = handle
+        for f in frames[:2]:
+            bh.render(f.camera, f.scene, opt, rgba=buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in frames:
+            bh.render(f.camera, f.scene, opt, rgba=buf)
+        torch.cuda.synchronize()
+        res[name] = len(frames) * 3840 * 2160 / (time.perf_counter() - t0) / 1e6
+    n_sur = 0
+    for f in frames:
+        opt = bh.options(precision=bh.FP32)
+        opt.surrogate = sur.handle
+        bh.render(f.camera, f.scene, opt, rgba=buf)
+        n_sur += bh.last_counts()["surrogate"]
+    share = n_sur / (len(frames) * 3840 * 2160)
+    print(f"surrogate gain: integrator {res['integrator']:.0f} Mrays/s, with surrogate "
+          f"{res['surrogate']:.0f} Mrays/s, ratio {res['surrogate'] / res['integrator']:.3f}, "
+          f"surrogate share {share:.3f}", flush=True)
+    assert share > 0.0
