@@ -154,6 +154,46 @@ bh_status bh_reserve(int64_t n);
 bh_status bh_last_counts(int64_t counts[4], void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched rendering for serving: many requests (each a camera, a scene and an
+ * output image) traced together.  All requests' rays share one index space:
+ * one set-up launch, ONE persistent integrator launch whose wavefronts pull
+ * rays of every request from the same queue (so small and large requests
+ * keep the whole chip busy), and one shading launch that records each
+ * request's completion on the device clock.  With use_graph the sequence is
+ * captured once into a hipGraph and each bh_batch_launch replays it.  Output
+ * pixels are bit-identical to bh_render of each request with the same options.
+ * The surrogate is not used in batches.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    bh_camera cam;
+    bh_scene  scene;
+    float*    rgba;        /* device, height*width*4 floats, written by each launch */
+} bh_request;
+
+typedef struct {
+    int64_t requests, rays;
+    double  makespan_ms;   /* last request's completion after the batch start */
+    double  p50_ms, p99_ms, min_ms;  /* per-request completion times */
+    double  mrays_per_s;   /* rays / makespan */
+} bh_batch_summary;
+
+typedef struct bh_batch bh_batch;
+
+/* Validates the requests (as bh_render), allocates the batch's device tables
+ * and per-ray workspace (~60 bytes per ray), and with use_graph != 0 captures
+ * the launch sequence into a hipGraph.  The request array is copied; the
+ * output pointers are kept.  Synchronous. */
+bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, int use_graph,
+                          bh_batch** out);
+/* Enqueues one execution of the batch on `stream`. */
+bh_status bh_batch_launch(bh_batch* b, void* stream);
+/* Waits for the last launch and summarises its per-request completion times. */
+bh_status bh_batch_stats(bh_batch* b, bh_batch_summary* st);
+/* Per-request completion times (ms after the batch start) of the last launch. */
+bh_status bh_batch_latencies(bh_batch* b, double* host_ms, int n);
+bh_status bh_batch_destroy(bh_batch* b);
+
+/* ---------------------------------------------------------------------------
  * Learned surrogate of the sweep (an extension of the paper's method): an MLP
  * 2 -> 128 -> 128 -> 128 -> 2 (ReLU) maps (b/M, r0/M) of an ingoing ray to the
  * exit azimuth on the sky sphere at r_sky = 1000 M (as a residual over the

@@ -43,6 +43,16 @@ class Options(C.Structure):
                 ("surrogate", C.c_void_p)]
 
 
+class Request(C.Structure):
+    _fields_ = [("cam", Camera), ("scene", Scene), ("rgba", C.c_void_p)]
+
+
+class BatchSummary(C.Structure):
+    _fields_ = [("requests", C.c_int64), ("rays", C.c_int64), ("makespan_ms", C.c_double),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("min_ms", C.c_double),
+                ("mrays_per_s", C.c_double)]
+
+
 class Adam(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
@@ -94,6 +104,14 @@ def lib():
         "bh_surrogate_trust": [vp, vp, i64],
         "bh_surrogate_set_trust": [vp, vp, i64],
     }
+    sigs.update({
+        "bh_batch_create": [C.POINTER(Request), C.c_int, C.POINTER(Options), C.c_int,
+                            C.POINTER(C.c_void_p)],
+        "bh_batch_launch": [vp, vp],
+        "bh_batch_stats": [vp, C.POINTER(BatchSummary)],
+        "bh_batch_latencies": [vp, vp, C.c_int],
+        "bh_batch_destroy": [vp],
+    })
     for name, args in sigs.items():
         fn = getattr(L, name)
         fn.argtypes = args
@@ -307,3 +325,60 @@ class Surrogate:
         m = np.ascontiguousarray(m, np.uint8)
         assert m.shape == TRUST_SHAPE
         check(lib().bh_surrogate_set_trust(self.handle, m.ctypes.data, m.size))
+
+
+# -- batched rendering --------------------------------------------------------
+
+class Batch:
+    """A set of render requests traced together (one persistent integrator
+    launch for all of them), optionally replayed from a captured hipGraph.
+    ``frames`` are inputs.Frame; ``images`` the matching (H, W, 4) float32
+    device tensors (allocated if None)."""
+
+    def __init__(self, frames, opt: Options | None = None, use_graph: bool = True, images=None,
+                 device="cuda"):
+        import torch
+        self.frames = list(frames)
+        if images is None:
+            images = [torch.empty((f.camera.height, f.camera.width, 4), dtype=torch.float32,
+                                  device=device) for f in self.frames]
+        self.images = images
+        reqs = (Request * len(self.frames))()
+        for k, (f, img) in enumerate(zip(self.frames, images)):
+            assert img.dtype == torch.float32 and img.is_contiguous()
+            assert img.numel() == f.camera.width * f.camera.height * 4
+            reqs[k] = Request(camera_struct(f.camera), scene_struct(f.scene), img.data_ptr())
+        self.opt = opt or options()
+        h = C.c_void_p()
+        check(lib().bh_batch_create(reqs, len(self.frames), C.byref(self.opt), 1 if use_graph else 0,
+                                    C.byref(h)))
+        self.handle = h
+
+    @property
+    def rays(self) -> int:
+        return sum(f.camera.width * f.camera.height for f in self.frames)
+
+    def launch(self, stream=None):
+        check(lib().bh_batch_launch(self.handle, _stream(stream)))
+
+    def stats(self) -> dict:
+        st = BatchSummary()
+        check(lib().bh_batch_stats(self.handle, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in BatchSummary._fields_}
+
+    def latencies(self):
+        import numpy as np
+        out = np.empty(len(self.frames), np.float64)
+        check(lib().bh_batch_latencies(self.handle, out.ctypes.data, len(self.frames)))
+        return out
+
+    def close(self):
+        if self.handle:
+            check(lib().bh_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -231,6 +232,43 @@ bh::Out dev_out(const bh_ray_out* o) {
 
 int auto_chunk(const bh_options* o) { return o->chunk > 0 ? o->chunk : 256; }
 
+bh_status check_camera(const bh_camera* cam, const bh_scene* scene) {
+    if (!cam) return fail(BH_ERR_ARG, "camera is NULL");
+    if (cam->width < 1 || cam->height < 1) return fail(BH_ERR_ARG, "width and height must be >= 1");
+    if ((int64_t)cam->width * cam->height > INT32_MAX)
+        return fail(BH_ERR_ARG, "image must have < 2^31 pixels");
+    if (!(isfinite(cam->r) && cam->r > 3.0 * scene->M))
+        return fail(BH_ERR_ARG, "camera must be outside the photon sphere (r > 3M)");
+    if (!(cam->r < scene->r_sky)) return fail(BH_ERR_ARG, "camera must be inside the sky sphere");
+    if (!(isfinite(cam->fov_deg) && cam->fov_deg > 0.0 && cam->fov_deg < 180.0))
+        return fail(BH_ERR_ARG, "fov_deg must be in (0, 180)");
+    if (!isfinite(cam->incl_deg) || !isfinite(cam->azim_deg))
+        return fail(BH_ERR_ARG, "camera angles must be finite");
+    return BH_OK;
+}
+
+// Camera basis (per frame): position r (sin i cos a, sin i sin a, cos i),
+// forward = -position/r, up = -e_theta, right = forward x up.
+bh::DevCam make_cam(const bh_camera* cam) {
+    const double inc = cam->incl_deg * kPi / 180.0, az = cam->azim_deg * kPi / 180.0;
+    const double ph[3] = {sin(inc) * cos(az), sin(inc) * sin(az), cos(inc)};
+    bh::DevCam c{};
+    for (int k = 0; k < 3; ++k) {
+        c.pos[k] = cam->r * ph[k];
+        c.fwd[k] = -ph[k];
+    }
+    c.up[0] = -cos(inc) * cos(az);
+    c.up[1] = -cos(inc) * sin(az);
+    c.up[2] = sin(inc);
+    c.right[0] = c.fwd[1] * c.up[2] - c.fwd[2] * c.up[1];
+    c.right[1] = c.fwd[2] * c.up[0] - c.fwd[0] * c.up[2];
+    c.right[2] = c.fwd[0] * c.up[1] - c.fwd[1] * c.up[0];
+    c.tan_half = tan(0.5 * cam->fov_deg * kPi / 180.0);
+    c.W = cam->width;
+    c.H = cam->height;
+    return c;
+}
+
 // The shared sequence: reset counters, set-up, integrate, shade.
 bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const bh_scene* scene,
               const bh_options* opt, float* rgba, const bh_ray_out* out, hipStream_t stream) {
@@ -318,42 +356,14 @@ bh_status bh_trace_rays(const double* origin, const double* dir, int64_t n, cons
 
 bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
                     float* rgba, const bh_ray_out* per_pixel, void* stream) {
-    if (!cam) return fail(BH_ERR_ARG, "camera is NULL");
     bh_status st = check_scene(scene);
     if (st != BH_OK) return st;
     if ((st = check_opt(opt)) != BH_OK) return st;
+    if ((st = check_camera(cam, scene)) != BH_OK) return st;
     if (!rgba) return fail(BH_ERR_ARG, "rgba is NULL");
-    if (cam->width < 1 || cam->height < 1) return fail(BH_ERR_ARG, "width and height must be >= 1");
-    const int64_t n = (int64_t)cam->width * cam->height;
-    if (n > INT32_MAX) return fail(BH_ERR_ARG, "image must have < 2^31 pixels");
-    if (!(isfinite(cam->r) && cam->r > 3.0 * scene->M))
-        return fail(BH_ERR_ARG, "camera must be outside the photon sphere (r > 3M)");
-    if (!(cam->r < scene->r_sky)) return fail(BH_ERR_ARG, "camera must be inside the sky sphere");
-    if (!(isfinite(cam->fov_deg) && cam->fov_deg > 0.0 && cam->fov_deg < 180.0))
-        return fail(BH_ERR_ARG, "fov_deg must be in (0, 180)");
-    if (!isfinite(cam->incl_deg) || !isfinite(cam->azim_deg))
-        return fail(BH_ERR_ARG, "camera angles must be finite");
-
-    // Camera basis (per frame): position, forward = -position, up = -e_theta,
-    // right = forward x up.
-    const double inc = cam->incl_deg * kPi / 180.0, az = cam->azim_deg * kPi / 180.0;
-    const double ph[3] = {sin(inc) * cos(az), sin(inc) * sin(az), cos(inc)};
     bh::Source src{};
-    src.n = n;
-    bh::DevCam& c = src.cam;
-    for (int k = 0; k < 3; ++k) {
-        c.pos[k] = cam->r * ph[k];
-        c.fwd[k] = -ph[k];
-    }
-    c.up[0] = -cos(inc) * cos(az);
-    c.up[1] = -cos(inc) * sin(az);
-    c.up[2] = sin(inc);
-    c.right[0] = c.fwd[1] * c.up[2] - c.fwd[2] * c.up[1];
-    c.right[1] = c.fwd[2] * c.up[0] - c.fwd[0] * c.up[2];
-    c.right[2] = c.fwd[0] * c.up[1] - c.fwd[1] * c.up[0];
-    c.tan_half = tan(0.5 * cam->fov_deg * kPi / 180.0);
-    c.W = cam->width;
-    c.H = cam->height;
+    src.n = (int64_t)cam->width * cam->height;
+    src.cam = make_cam(cam);
     return run(src, false, 1.0 / cam->r, scene, opt, rgba, per_pixel, (hipStream_t)stream);
 }
 
@@ -381,6 +391,208 @@ bh_status bh_last_counts(int64_t counts[4], void* stream) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     for (int k = 0; k < 4; ++k) counts[k] = (int64_t)h[k];
+    return BH_OK;
+}
+
+}  // extern "C"
+
+struct bh_batch {
+    int device = 0;
+    int nreq = 0;
+    int64_t total = 0;
+    int use_graph = 0;
+    void* base = nullptr;
+    bh::BatchDev dev{};
+    bh::Work w{};
+    bh::DevTol tol{};
+    int precision = 0, grid_blocks = 0, chunk = 256, cus = 256;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;
+    double clock_hz = 1e8;
+};
+
+extern "C" {
+
+bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, int use_graph,
+                          bh_batch** out) {
+    if (!out) return fail(BH_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!reqs || n < 1) return fail(BH_ERR_ARG, "need at least one request");
+    bh_status st = check_opt(opt);
+    if (st != BH_OK) return st;
+    if (opt->surrogate) return fail(BH_ERR_UNSUPPORTED, "batches do not route to the surrogate");
+    std::vector<bh::ReqDev> req(n);
+    std::vector<bh::BatchConst> bc(n);
+    std::vector<int64_t> off(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+        const bh_request& q = reqs[r];
+        if ((st = check_scene(&q.scene)) != BH_OK) return fail(st, "request %d: %s", r, bh_last_error());
+        if ((st = check_camera(&q.cam, &q.scene)) != BH_OK)
+            return fail(st, "request %d: %s", r, bh_last_error());
+        if (!q.rgba) return fail(BH_ERR_ARG, "request %d: rgba is NULL", r);
+        req[r].cam = make_cam(&q.cam);
+        req[r].sc = dev_scene(&q.scene);
+        req[r].rt = dev_route(opt, &q.scene);
+        req[r].rgba = q.rgba;
+        const bh::DevTol t = dev_tol(opt, &q.scene);
+        bc[r].M = q.scene.M;
+        bc[r].usky = req[r].sc.u_sky;
+        bc[r].urin = req[r].sc.urin;
+        bc[r].urout = req[r].sc.urout;
+        bc[r].u0 = 1.0 / q.cam.r;
+        bc[r].atol64 = t.atol64;
+        bc[r].atol32 = t.atol32;
+        bc[r].pad = 0.0f;
+        off[r + 1] = off[r] + (int64_t)q.cam.width * q.cam.height;
+    }
+    if (off[n] > INT32_MAX) return fail(BH_ERR_ARG, "a batch must have < 2^31 rays");
+    bh_batch* b = new bh_batch();
+    b->nreq = n;
+    b->total = off[n];
+    b->use_graph = use_graph ? 1 : 0;
+    b->tol = dev_tol(opt, &reqs[0].scene);
+    b->precision = opt->precision;
+    b->grid_blocks = opt->grid_blocks;
+    b->chunk = auto_chunk(opt);
+    auto cleanup = [b](bh_status s) {
+        bh_batch_destroy(b);
+        return s;
+    };
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && v > 0)
+        b->cus = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, b->device) == hipSuccess && v > 0)
+        b->clock_hz = 1e3 * v;
+    const int64_t N = b->total;
+    const size_t sz16 = align256((size_t)N * 16), sz4 = align256((size_t)N * 4),
+                 sz1 = align256((size_t)N), szc = align256(sizeof(int32_t) * bh::kCtrInts);
+    const size_t tables = align256(sizeof(int64_t) * (n + 1)) + align256(sizeof(bh::ReqDev) * n) +
+                          align256(sizeof(bh::BatchConst) * n) + align256(8 * (size_t)n) +
+                          align256(8 * (size_t)(n + 1));
+    const size_t total = 3 * sz16 + 3 * sz4 + sz1 + szc + tables;
+    e = hipMalloc(&b->base, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b->base = nullptr;
+        return cleanup(fail(BH_ERR_NOMEM, "batch buffers of %zu bytes", total));
+    }
+    char* c = (char*)b->base;
+    b->w.rec = (double2*)c; c += sz16;
+    b->w.res = (double2*)c; c += sz16;
+    b->w.q64rec = (double2*)c; c += sz16;
+    b->w.clst = (int32_t*)c; c += sz4;
+    b->w.q64 = (int32_t*)c; c += sz4;
+    b->w.rq = (int32_t*)c; c += sz4;
+    b->w.path = (uint8_t*)c; c += sz1;
+    b->w.ctr = (int32_t*)c; c += szc;
+    b->w.u0 = nullptr;
+    b->w.sur = nullptr;
+    int64_t* d_off = (int64_t*)c; c += align256(sizeof(int64_t) * (n + 1));
+    bh::ReqDev* d_req = (bh::ReqDev*)c; c += align256(sizeof(bh::ReqDev) * n);
+    bh::BatchConst* d_bc = (bh::BatchConst*)c; c += align256(sizeof(bh::BatchConst) * n);
+    unsigned long long* d_done = (unsigned long long*)c; c += align256(8 * (size_t)n);
+    unsigned long long* d_stamp = (unsigned long long*)c;
+    if ((e = hipMemcpy(d_off, off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_req, req.data(), sizeof(bh::ReqDev) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_bc, bc.data(), sizeof(bh::BatchConst) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(d_stamp, 0, 8 * (size_t)(n + 1))) != hipSuccess)
+        return cleanup(hip_fail(e, "batch tables"));
+    bh::BatchDev& d = b->dev;
+    d.nreq = n;
+    d.total = N;
+    d.off = d_off;
+    d.req = d_req;
+    d.bconst = d_bc;
+    d.done = d_done;
+    d.stamp = d_stamp;
+    d.req_host0 = req[0].sc;
+    if (b->use_graph) {
+        // Capture the whole sequence (counter resets are kernels, not memsets)
+        // once; each launch replays it.
+        if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
+            return cleanup(hip_fail(e, "capture stream"));
+        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess)
+            return cleanup(hip_fail(e, "hipStreamBeginCapture"));
+        e = bh::launch_batch(d, b->w, b->tol, b->precision, b->cus, b->grid_blocks, b->chunk, b->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+        b->graph = g;
+        if (e != hipSuccess) return cleanup(hip_fail(e, "batch capture"));
+        if (e2 != hipSuccess) return cleanup(hip_fail(e2, "hipStreamEndCapture"));
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+            return cleanup(hip_fail(e, "hipGraphInstantiate"));
+    }
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return cleanup(hip_fail(e, "sync"));
+    *out = b;
+    return BH_OK;
+}
+
+bh_status bh_batch_launch(bh_batch* b, void* stream) {
+    if (!b) return fail(BH_ERR_ARG, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (b->use_graph)
+        e = hipGraphLaunch(b->exec, s);
+    else
+        e = bh::launch_batch(b->dev, b->w, b->tol, b->precision, b->cus, b->grid_blocks, b->chunk, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    b->last = s;
+    return BH_OK;
+}
+
+bh_status bh_batch_stats(bh_batch* b, bh_batch_summary* st) {
+    if (!b || !st) return fail(BH_ERR_ARG, "batch and stats are required");
+    hipError_t e = hipStreamSynchronize(b->last);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    std::vector<unsigned long long> stamp(b->nreq + 1);
+    e = hipMemcpy(stamp.data(), b->dev.stamp, 8 * stamp.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "stamps");
+    std::vector<double> lat(b->nreq);
+    const unsigned long long t0 = stamp[b->nreq];
+    for (int r = 0; r < b->nreq; ++r)
+        lat[r] = stamp[r] >= t0 ? 1e3 * (double)(stamp[r] - t0) / b->clock_hz : -1.0;
+    std::vector<double> sorted = lat;
+    std::sort(sorted.begin(), sorted.end());
+    auto pct = [&sorted](double p) {
+        size_t k = (size_t)ceil(p * sorted.size()) ;
+        k = k == 0 ? 0 : k - 1;
+        if (k >= sorted.size()) k = sorted.size() - 1;
+        return sorted[k];
+    };
+    st->requests = b->nreq;
+    st->rays = b->total;
+    st->makespan_ms = sorted.back();
+    st->p50_ms = pct(0.50);
+    st->p99_ms = pct(0.99);
+    st->min_ms = sorted.front();
+    st->mrays_per_s = st->makespan_ms > 0 ? (double)b->total / (st->makespan_ms * 1e-3) / 1e6 : 0.0;
+    return BH_OK;
+}
+
+bh_status bh_batch_latencies(bh_batch* b, double* host_ms, int n) {
+    if (!b || !host_ms || n != b->nreq) return fail(BH_ERR_ARG, "need nreq doubles");
+    hipError_t e = hipStreamSynchronize(b->last);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    std::vector<unsigned long long> stamp(b->nreq + 1);
+    e = hipMemcpy(stamp.data(), b->dev.stamp, 8 * stamp.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "stamps");
+    for (int r = 0; r < n; ++r)
+        host_ms[r] = 1e3 * ((double)stamp[r] - (double)stamp[n]) / b->clock_hz;
+    return BH_OK;
+}
+
+bh_status bh_batch_destroy(bh_batch* b) {
+    if (!b) return BH_OK;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->base) (void)hipFree(b->base);
+    delete b;
     return BH_OK;
 }
 

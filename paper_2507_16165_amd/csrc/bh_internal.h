@@ -88,6 +88,7 @@ struct Work {
     double2* rec;             // start record {w0, phi1}; w0 = NaN: not in the main queue
     double2* res;             // result record {phi_end, r_hit}
     double2* sur;             // surrogate rays: {b, w0}
+    int32_t* rq;              // batch: request index of each ray
     int32_t* clst;            // class | (step evaluations << 3)
     uint8_t* path;
     int32_t* q64;             // FP64 band queue (FP32 mode): ray indices ...
@@ -124,7 +125,34 @@ struct Source {
     DevCam cam;
 };
 
+// Batched rendering: per-request constants of the integrator (staged in LDS)
+// and of set-up/shading.
+struct BatchConst {
+    double M, usky, urin, urout, u0, atol64;
+    float atol32, pad;
+};
+
+struct ReqDev {
+    DevCam cam;
+    DevScene sc;
+    DevRoute rt;
+    float* rgba;
+};
+
+struct BatchDev {
+    int nreq;
+    int64_t total;                 // rays of all requests
+    const int64_t* off;            // nreq + 1 ray offsets
+    const ReqDev* req;
+    const BatchConst* bconst;
+    unsigned long long* done;      // pixels shaded per request
+    unsigned long long* stamp;     // finish clock per request; stamp[nreq] = start
+    DevScene req_host0;            // unused placeholder scene for the integrator args
+};
+
 // Launch helpers (defined in bh_kernels.hip).
+hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int precision,
+                        int cus, int grid_blocks, int chunk, hipStream_t s);
 hipError_t launch_reset(int32_t* ctr, hipStream_t s);
 hipError_t launch_setup(const Source& src, const DevScene& sc, const DevRoute& rt, const Work& w,
                         double* out_b, hipStream_t s);

@@ -107,70 +107,74 @@ __global__ void k_reset(int32_t* ctr) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double nan_d() { return __builtin_nan(""); }
 
-__global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRoute rt, Work w,
-                                                  double* out_b) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < src.n;
+// Set-up of ray i (index into the per-ray workspace) with origin o and
+// direction dv: plane reduction, impact parameter, first disk-plane crossing,
+// routing.  Returns whether the ray joins the FP64 band queue.
+__device__ __forceinline__ bool setup_ray(const double o[3], const double dv[3], const DevScene& sc,
+                                          const DevRoute& rt, int64_t i, const Work& w,
+                                          double* out_b, double& w0, double& phi1) {
     bool to_q64 = false;
-    double w0 = 0.0, phi1 = 0.0;
-    if (valid) {
-        double o[3], dv[3];
-        source_ray(src, i, o, dv);
-        const Basis B = plane_basis(o, dv, sc.M, sc.r_sky);
-        uint8_t path = PATH_NONE, cls = INVALID;
-        double phi_end = 0.0, b = 0.0;
-        if (B.ok && B.radial) {
-            // Radial ray: inward is captured (flat space: straight through
-            // the centre to the antipode); outward escapes along e1.
-            if (B.c < 0.0) {
-                cls = sc.M > 0.0 ? CAPTURED : SKY;
-                phi_end = sc.M > 0.0 ? 0.0 : kPi;
-            } else {
-                cls = SKY;
-            }
-        } else if (B.ok) {
-            const double u0 = 1.0 / B.r0;
-            w0 = -u0 * B.c / B.s;
-            // First integral of Eq. (1): w^2 + u^2 - 2 M u^3 = 1/b^2.
-            const double E0 = w0 * w0 + u0 * u0 - 2.0 * sc.M * u0 * u0 * u0;
-            b = 1.0 / sqrt(E0);
-            const double bc = kBcrit * sc.M;
-            if (w.u0) w.u0[i] = u0;
-            phi1 = sc.has_disk ? first_crossing(B.e1[2], B.e2[2]) : __builtin_inf();
-            // Surrogate: ingoing rays above the band whose periapsis lies
-            // outside the disk (u_out^2 - 2 M u_out^3 > 1/b^2: the ray turns
-            // before reaching r_out), in a bin the trust map accepts.
-            bool sur = false;
-            if (rt.trust && B.c < 0.0 && b > bc + rt.band &&
-                (!sc.has_disk || sc.urout * sc.urout * (1.0 - 2.0 * sc.M * sc.urout) > E0)) {
-                const int bin = trust_bin((float)(b / sc.M), rt.r0m);
-                sur = bin >= 0 && rt.trust[bin] != 0;
-            }
-            if (rt.analytic_capture && !sc.has_disk && B.c < 0.0 && b < bc - rt.band) {
-                cls = CAPTURED;  // below the potential peak: falls in, no disk to hit
-            } else if (sur) {
-                path = PATH_SUR;
-                w.sur[i] = make_double2(b, w0);
-            } else if (rt.precision == 1 && fabs(b - bc) < rt.band) {
-                path = PATH_FP64;
-                to_q64 = true;
-            } else {
-                path = rt.precision == 1 ? PATH_FP32 : PATH_FP64;
-            }
+    const Basis B = plane_basis(o, dv, sc.M, sc.r_sky);
+    uint8_t path = PATH_NONE, cls = INVALID;
+    double phi_end = 0.0, b = 0.0;
+    w0 = 0.0;
+    phi1 = 0.0;
+    if (B.ok && B.radial) {
+        // Radial ray: inward is captured (flat space: straight through the
+        // centre to the antipode); outward escapes along e1.
+        if (B.c < 0.0) {
+            cls = sc.M > 0.0 ? CAPTURED : SKY;
+            phi_end = sc.M > 0.0 ? 0.0 : kPi;
+        } else {
+            cls = SKY;
         }
-        w.path[i] = path;
-        // The main queue is the index range itself; its record marks rays
-        // that belong to another path (band, set-up only) with w0 = NaN.
-        const bool main = path != PATH_NONE && path != PATH_SUR && !to_q64;
-        w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
-        if (path == PATH_NONE) {
-            w.res[i] = make_double2(phi_end, 0.0);
-            w.clst[i] = cls;
+    } else if (B.ok) {
+        const double u0 = 1.0 / B.r0;
+        w0 = -u0 * B.c / B.s;
+        // First integral of Eq. (1): w^2 + u^2 - 2 M u^3 = 1/b^2.
+        const double E0 = w0 * w0 + u0 * u0 - 2.0 * sc.M * u0 * u0 * u0;
+        b = 1.0 / sqrt(E0);
+        const double bc = kBcrit * sc.M;
+        if (w.u0) w.u0[i] = u0;
+        phi1 = sc.has_disk ? first_crossing(B.e1[2], B.e2[2]) : __builtin_inf();
+        // Surrogate: ingoing rays above the band whose periapsis lies outside
+        // the disk (u_out^2 - 2 M u_out^3 > 1/b^2: the ray turns before
+        // reaching r_out), in a bin the trust map accepts.
+        bool sur = false;
+        if (rt.trust && B.c < 0.0 && b > bc + rt.band &&
+            (!sc.has_disk || sc.urout * sc.urout * (1.0 - 2.0 * sc.M * sc.urout) > E0)) {
+            const int bin = trust_bin((float)(b / sc.M), rt.r0m);
+            sur = bin >= 0 && rt.trust[bin] != 0;
         }
-        if (out_b) out_b[i] = b;
+        if (rt.analytic_capture && !sc.has_disk && B.c < 0.0 && b < bc - rt.band) {
+            cls = CAPTURED;  // below the potential peak: falls in, no disk to hit
+        } else if (sur) {
+            path = PATH_SUR;
+            w.sur[i] = make_double2(b, w0);
+        } else if (rt.precision == 1 && fabs(b - bc) < rt.band) {
+            path = PATH_FP64;
+            to_q64 = true;
+        } else {
+            path = rt.precision == 1 ? PATH_FP32 : PATH_FP64;
+        }
     }
-    // Wave-aggregated append to the FP64 band queue: one atomic per wavefront
-    // that holds band rays (a fraction of a percent of all wavefronts).
+    w.path[i] = path;
+    // The main queue is the index range itself; its record marks rays that
+    // belong to another path (band, surrogate, set-up only) with w0 = NaN.
+    const bool main = path != PATH_NONE && path != PATH_SUR && !to_q64;
+    w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
+    if (path == PATH_NONE) {
+        w.res[i] = make_double2(phi_end, 0.0);
+        w.clst[i] = cls;
+    }
+    if (out_b) out_b[i] = b;
+    return to_q64;
+}
+
+// Wave-aggregated append to the FP64 band queue: one atomic per wavefront
+// that holds band rays (a fraction of a percent of all wavefronts).
+__device__ __forceinline__ void append_band(bool to_q64, int64_t i, double w0, double phi1,
+                                            const Work& w) {
     const uint64_t m = __ballot(to_q64);
     if (m) {
         const int leader = __ffsll((unsigned long long)m) - 1;
@@ -183,6 +187,57 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
             w.q64rec[slot] = make_double2(w0, phi1);
         }
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRoute rt, Work w,
+                                                  double* out_b) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool to_q64 = false;
+    double w0 = 0.0, phi1 = 0.0;
+    if (i < src.n) {
+        double o[3], dv[3];
+        source_ray(src, i, o, dv);
+        to_q64 = setup_ray(o, dv, sc, rt, i, w, out_b, w0, phi1);
+    }
+    append_band(to_q64, i, w0, phi1, w);
+}
+
+// Request of batch ray g: the last r with off[r] <= g (binary search over the
+// request offsets staged in LDS).
+__device__ __forceinline__ int find_req(const int64_t* off, int nreq, int64_t g) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void stage_offsets(const BatchDev& b, int64_t* s_off) {
+    for (int k = threadIdx.x; k <= b.nreq; k += blockDim.x) s_off[k] = b.off[k];
+    __syncthreads();
+}
+
+// Batch set-up: all requests' rays in one index space; each ray also records
+// its request for the integrator.
+__global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
+    extern __shared__ int64_t s_off[];
+    stage_offsets(b, s_off);
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool to_q64 = false;
+    double w0 = 0.0, phi1 = 0.0;
+    if (g < b.total) {
+        const int r = find_req(s_off, b.nreq, g);
+        const ReqDev& q = b.req[r];
+        double o[3], dv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) o[k] = q.cam.pos[k];
+        camera_dir(q.cam, g - s_off[r], dv);
+        w.rq[g] = r;
+        to_q64 = setup_ray(o, dv, q.sc, q.rt, g, w, nullptr, w0, phi1);
+    }
+    append_band(to_q64, g, w0, phi1, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,6 +322,8 @@ struct IntegArgs {
     DevTol tol;
     Work w;
     int chunk;
+    const BatchConst* bconst; // batch: per-request constants (global), nreq entries
+    int nreq;
 };
 
 // 1/x in FP64 from the hardware reciprocal estimate and one Newton step
@@ -291,18 +348,25 @@ __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x
 // re-step of the sky crossing -- and all outcomes (accept / reject, disk
 // landing, horizon, sky crossing, caps) are applied with selects, so the
 // wavefront stays converged except for the store of a finished ray.
-template <typename T, bool VIRTUAL>
+//
+// BATCH: rays of several requests share the queue; each ray's request index
+// selects its scene constants from a table staged in LDS (`bct`).
+template <typename T, bool VIRTUAL, bool BATCH>
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
-                          int nslices, T rtol, T atol, T ntol) {
+                          int nslices, T rtol, T atol_in, T ntol,
+                          const BatchConst* __restrict__ bct) {
     const int lane = lane_id();
-    const T M3 = T(3.0 * a.sc.M);
-    const double twoM = 2.0 * a.sc.M;
-    const T usky = T(a.sc.u_sky);
+    // scene constants: wave-uniform for one frame, per lane for a batch
+    T M3 = T(3.0 * a.sc.M);
+    double twoM = 2.0 * a.sc.M;
+    T usky = T(a.sc.u_sky);
+    T urin = T(a.sc.urin), urout = T(a.sc.urout);
+    T atol = atol_in;
     const T h0 = T(a.tol.h0), hmax = T(a.tol.hmax);
-    const T urin = T(a.sc.urin), urout = T(a.sc.urout);
     const double max_phi = a.tol.max_phi;
     const int max_steps = a.tol.max_steps;
+    int pf_rq = 0;
 
     // ray state
     T u = T(0), w = T(0), g = T(0), h = T(0), hh = T(0);
@@ -324,6 +388,16 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             pf_valid = false;
             if (!VIRTUAL || pf.x == pf.x) {
                 id = pf_id;
+                if (BATCH) {
+                    const BatchConst& c = bct[pf_rq];
+                    M3 = T(3.0 * c.M);
+                    twoM = 2.0 * c.M;
+                    usky = T(c.usky);
+                    urin = T(c.urin);
+                    urout = T(c.urout);
+                    atol = sizeof(T) == 8 ? T(c.atol64) : T(c.atol32);
+                    pf_u0 = c.u0;
+                }
                 u = T(pf_u0);
                 w = T(pf.x);
                 g = g_of(M3, u);
@@ -366,7 +440,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                     const int64_t pos = cnext + rank;
                     pf_id = VIRTUAL ? (int)pos : queue[pos];
                     pf = VIRTUAL ? a.w.rec[pos] : qrec[pos];
-                    if (a.u0) pf_u0 = a.u0[pf_id];
+                    if (BATCH) pf_rq = a.w.rq[pf_id];
+                    else if (a.u0) pf_u0 = a.u0[pf_id];
                     pf_valid = true;
                 }
                 cnext += min((int64_t)__popcll(need), avail);
@@ -456,10 +531,22 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     }
 }
 
+// Stages the batch's per-request scene constants in LDS (batch kernels only).
+template <bool BATCH>
+__device__ __forceinline__ const BatchConst* stage_consts(const IntegArgs& a) {
+    if (!BATCH) return nullptr;
+    extern __shared__ BatchConst s_bc[];
+    for (int k = threadIdx.x; k < a.nreq; k += blockDim.x) s_bc[k] = a.bconst[k];
+    __syncthreads();
+    return s_bc;
+}
+
 // FP64 mode: one pass over all rays tagged FP64.
+template <bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
-    run_queue<double, true>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices, a.tol.rtol64,
-                            a.tol.atol64, a.tol.newton64);
+    const BatchConst* bct = stage_consts<BATCH>(a);
+    run_queue<double, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
+                                   a.tol.rtol64, a.tol.atol64, a.tol.newton64, bct);
 }
 
 // FP32 mode.  The first `band_blocks` blocks first drain the FP64 queue of
@@ -469,29 +556,31 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
 // SIMDs fill the gaps and the band ends inside the FP32 work instead of
 // trailing it.  The kernel is held to 64 VGPRs (8 waves per SIMD for the FP32
 // rays); the FP64 code spills a few registers, which only band waves pay.
+template <bool BATCH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
 k_integrate_fp32(IntegArgs a, int band_blocks) {
+    const BatchConst* bct = stage_consts<BATCH>(a);
     if ((int)blockIdx.x < band_blocks) {
         __builtin_amdgcn_s_setprio(3);
         IntegArgs ab = a;
         ab.chunk = 64;
-        run_queue<double, false>(ab, a.w.q64, a.w.q64rec, a.w.ctr[kCtrBandSize], &a.w.ctr[kCtrBand],
-                                 1, a.tol.rtol64, a.tol.atol64, a.tol.newton64);
+        run_queue<double, false, BATCH>(ab, a.w.q64, a.w.q64rec, a.w.ctr[kCtrBandSize],
+                                        &a.w.ctr[kCtrBand], 1, a.tol.rtol64, a.tol.atol64,
+                                        a.tol.newton64, bct);
         __builtin_amdgcn_s_setprio(0);
     }
-    run_queue<float, true>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices, a.tol.rtol32,
-                           a.tol.atol32, a.tol.newton32);
+    run_queue<float, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
+                                  a.tol.rtol32, a.tol.atol32, a.tol.newton32, bct);
 }
 
 // ---------------------------------------------------------------------------
 // Shading and output.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work w, float* rgba,
-                                                  Out out) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= src.n) return;
-    double o[3], dv[3];
-    source_ray(src, i, o, dv);
+// End vector and colour of workspace ray i with origin o and direction dv;
+// px (may be NULL) receives the RGBA value, out[oi] the per-ray record.
+__device__ __forceinline__ void shade_ray(const double o[3], const double dv[3],
+                                          const DevScene& sc, const Work& w, int64_t i,
+                                          float4* px_out, const Out& out, int64_t oi) {
     const Basis B = plane_basis(o, dv, sc.M, sc.r_sky);
     const int32_t cs = w.clst[i];
     const uint8_t cls = (uint8_t)(cs & 7);
@@ -505,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
     for (int k = 0; k < 3; ++k) s[k] = cphi * B.e1[k] + sphi * B.e2[k];
     if (cls == INVALID) s[0] = s[1] = s[2] = 0.0;
 
-    if (rgba) {
+    if (px_out) {
         float4 px = make_float4(0.f, 0.f, 0.f, 1.f);
         if (cls == SKY) {
             const double theta = atan2(hypot(s[0], s[1]), s[2]);
@@ -519,17 +608,64 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
             const double I = pow(r_hit / sc.rin, sc.power);
             px = make_float4((float)I, (float)(0.6 * I), (float)(0.2 * I), 1.f);
         }
-        reinterpret_cast<float4*>(rgba)[i] = px;
+        *px_out = px;
     }
-    if (out.cls) out.cls[i] = cls;
-    if (out.phi_end) out.phi_end[i] = phi;
-    if (out.r_hit) out.r_hit[i] = r_hit;
-    if (out.steps) out.steps[i] = cs >> 3;
-    if (out.path) out.path[i] = w.path[i];
+    if (out.cls) out.cls[oi] = cls;
+    if (out.phi_end) out.phi_end[oi] = phi;
+    if (out.r_hit) out.r_hit[oi] = r_hit;
+    if (out.steps) out.steps[oi] = cs >> 3;
+    if (out.path) out.path[oi] = w.path[i];
     if (out.exit_dir) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) out.exit_dir[3 * i + k] = s[k];
+        for (int k = 0; k < 3; ++k) out.exit_dir[3 * oi + k] = s[k];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work w, float* rgba,
+                                                  Out out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= src.n) return;
+    double o[3], dv[3];
+    source_ray(src, i, o, dv);
+    shade_ray(o, dv, sc, w, i, rgba ? reinterpret_cast<float4*>(rgba) + i : nullptr, out, i);
+}
+
+// Batch shading: each pixel goes to its request's image; the block that
+// completes a request records the device clock as the request's finish time.
+__global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
+    extern __shared__ int64_t s_off[];
+    stage_offsets(b, s_off);
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t g = g0 + threadIdx.x;
+    if (g < b.total) {
+        const int r = find_req(s_off, b.nreq, g);
+        const ReqDev& q = b.req[r];
+        const int64_t i = g - s_off[r];
+        double o[3], dv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) o[k] = q.cam.pos[k];
+        camera_dir(q.cam, i, dv);
+        shade_ray(o, dv, q.sc, w, g, reinterpret_cast<float4*>(q.rgba) + i, Out{}, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t g1 = min(g0 + kBlock, b.total);
+        if (g0 < g1) {
+            for (int r = find_req(s_off, b.nreq, g0); r < b.nreq && s_off[r] < g1; ++r) {
+                const int64_t lo = max(g0, s_off[r]), hi = min(g1, s_off[r + 1]);
+                if (hi <= lo) continue;
+                const unsigned long long cnt = (unsigned long long)(hi - lo);
+                const unsigned long long total = (unsigned long long)(s_off[r + 1] - s_off[r]);
+                if (atomicAdd(&b.done[r], cnt) + cnt == total) b.stamp[r] = wall_clock64();
+            }
+        }
+    }
+}
+
+// Batch start time and completion counters.
+__global__ void k_batch_begin(BatchDev b) {
+    for (int r = threadIdx.x; r < b.nreq; r += blockDim.x) b.done[r] = 0;
+    if (threadIdx.x == 0) b.stamp[b.nreq] = wall_clock64();
 }
 
 __global__ __launch_bounds__(kBlock) void k_count_paths(int64_t n, const uint8_t* path,
@@ -576,6 +712,18 @@ static int blocks_per_cu(K kernel, int* cache) {
     return *cache;
 }
 
+template <typename K>
+static int blocks_per_cu_lds(K kernel, size_t lds, int* cache) {
+    if (*cache == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, lds) != hipSuccess ||
+            nb < 1)
+            nb = 1;
+        *cache = nb;
+    }
+    return *cache;
+}
+
 static unsigned persistent_grid(int64_t n, int cus, int per_cu, int grid_blocks) {
     int64_t g = grid_blocks > 0 ? grid_blocks : (int64_t)cus * per_cu;
     const int64_t need = (n + kBlock - 1) / kBlock;
@@ -596,14 +744,56 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
     a.tol = tol;
     a.w = w;
     a.chunk = chunk;
+    a.bconst = nullptr;
+    a.nreq = 0;
     if (precision != 1) {
-        const unsigned g = persistent_grid(n, cus, blocks_per_cu(k_integrate_fp64, &occ64), grid_blocks);
-        k_integrate_fp64<<<g, kBlock, 0, s>>>(a);
+        const unsigned g =
+            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp64<false>, &occ64), grid_blocks);
+        k_integrate_fp64<false><<<g, kBlock, 0, s>>>(a);
     } else {
-        const unsigned g = persistent_grid(n, cus, blocks_per_cu(k_integrate_fp32, &occ32), grid_blocks);
+        const unsigned g =
+            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp32<false>, &occ32), grid_blocks);
         const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
-        k_integrate_fp32<<<g, kBlock, 0, s>>>(a, band_blocks);
+        k_integrate_fp32<false><<<g, kBlock, 0, s>>>(a, band_blocks);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int precision,
+                        int cus, int grid_blocks, int chunk, hipStream_t s) {
+    static int occ64 = 0, occ32 = 0;
+    k_batch_begin<<<1, 256, 0, s>>>(b);
+    k_reset<<<1, 64, 0, s>>>(w.ctr);
+    const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
+    if (b.total > 0) k_setup_batch<<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || b.total == 0) return e;
+    IntegArgs a;
+    a.n = b.total;
+    a.u0 = nullptr;
+    a.u0_uniform = 0.0;
+    a.sc = b.req_host0;  // placeholders; the batch kernels read per-request constants
+    a.tol = tol;
+    a.w = w;
+    a.chunk = chunk;
+    a.bconst = b.bconst;
+    a.nreq = b.nreq;
+    const size_t lds_c = sizeof(BatchConst) * b.nreq;
+    if (precision != 1) {
+        const unsigned g =
+            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp64<true>, lds_c, &occ64),
+                            grid_blocks);
+        k_integrate_fp64<true><<<g, kBlock, lds_c, s>>>(a);
+    } else {
+        const unsigned g =
+            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp32<true>, lds_c, &occ32),
+                            grid_blocks);
+        const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
+        k_integrate_fp32<true><<<g, kBlock, lds_c, s>>>(a, band_blocks);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_shade_batch<<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
     return hipGetLastError();
 }
 

@@ -102,3 +102,21 @@ def test_output_marshalling_on_host_tensors():
     assert ro.exit_dir == t["exit_dir"].data_ptr() and ro.steps == t["steps"].data_ptr()
     t, ro = api._alloc_out(4, ("cls",), "cpu")
     assert ro.b is None and ro.cls == t["cls"].data_ptr()
+
+
+def test_batch_argument_checks():
+    """Batch creation rejects bad arguments before touching the device."""
+    L = api.lib()
+    h = C.c_void_p()
+    o = api.options()
+    assert L.bh_batch_create(None, 0, C.byref(o), 0, C.byref(h)) == api.BH_ERR_ARG
+    reqs = (api.Request * 1)()
+    reqs[0] = api.Request(api.camera_struct(inputs.Camera(2.0, 90, 0, 60, 8, 8)),
+                          api.scene_struct(inputs.Scene(M=1.0)), 1)
+    assert L.bh_batch_create(reqs, 1, C.byref(o), 0, C.byref(h)) == api.BH_ERR_ARG
+    assert "request 0" in L.bh_last_error().decode()
+    reqs[0] = api.Request(api.camera_struct(inputs.Camera(30.0, 90, 0, 60, 8, 8)),
+                          api.scene_struct(inputs.Scene(M=1.0)), None)
+    assert L.bh_batch_create(reqs, 1, C.byref(o), 0, C.byref(h)) == api.BH_ERR_ARG
+    assert L.bh_batch_launch(None, None) == api.BH_ERR_ARG
+    assert L.bh_batch_destroy(None) == api.BH_OK

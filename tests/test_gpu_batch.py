@@ -1,0 +1,113 @@
+"""Batched rendering (one persistent integrator launch for many requests,
+optionally replayed from a hipGraph) against per-request bh_render, which the
+parity tests pin to the oracle; graph replays; latency statistics; autotuner."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2507_16165_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2507_16165_amd import api
+    api.lib()
+    return api
+
+
+def mixed_frames():
+    """Ragged sizes (not multiples of the block or chunk), with and without a
+    disk, different masses and distances, one 1x1 request."""
+    out = []
+    sizes = [(33, 17), (64, 64), (1, 1), (128, 96), (200, 150), (57, 301), (96, 96), (250, 250)]
+    rng = np.random.default_rng(12)
+    for k, (w, h) in enumerate(sizes):
+        M = float(rng.uniform(0.5, 2.0))
+        rho = float(rng.uniform(15.0, 120.0))
+        disk = (6.0, 20.0) if k % 2 == 0 else None
+        cam = inputs.Camera(rho * M, float(rng.uniform(0, 90)), float(rng.uniform(0, 360)), 60.0, w, h)
+        out.append(inputs.Frame(cam, inputs.scene_in_m(M, disk), f"m{k}"))
+    return out
+
+
+def _single(bh, frames, precision):
+    import torch
+    imgs = []
+    for f in frames:
+        rgba, _ = bh.render(f.camera, f.scene, bh.options(precision=precision))
+        imgs.append(rgba)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in imgs]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_per_request_renders(bh, precision, graph):
+    import torch
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    frames = mixed_frames()
+    want = _single(bh, frames, p)
+    b = bh.Batch(frames, bh.options(precision=p), use_graph=graph)
+    b.launch()
+    torch.cuda.synchronize()
+    for k, (img, ref) in enumerate(zip(b.images, want)):
+        np.testing.assert_array_equal(img.cpu().numpy(), ref, err_msg=f"request {k}")
+    st = b.stats()
+    assert st["requests"] == len(frames) and st["rays"] == b.rays
+    assert 0 <= st["min_ms"] <= st["p50_ms"] <= st["p99_ms"] <= st["makespan_ms"]
+    lat = b.latencies()
+    assert np.all(lat >= 0) and abs(lat.max() - st["makespan_ms"]) < 1e-9
+    b.close()
+
+
+def test_graph_replays_are_identical(bh):
+    """The captured graph replayed several times, with eager work and
+    synchronisation in between, reproduces the eager result every time."""
+    import torch
+    frames = mixed_frames()
+    want = _single(bh, frames, bh.FP32)
+    b = bh.Batch(frames, bh.options(precision=bh.FP32), use_graph=True)
+    for rep in range(4):
+        for img in b.images:
+            img.fill_(-1.0)
+        torch.cuda.synchronize()
+        b.launch()
+        torch.cuda.synchronize()
+        for k, (img, ref) in enumerate(zip(b.images, want)):
+            np.testing.assert_array_equal(img.cpu().numpy(), ref, err_msg=f"replay {rep} request {k}")
+        # eager work between replays on the same device
+        bh.render(frames[0].camera, frames[0].scene, bh.options(precision=bh.FP64))
+        torch.cuda.synchronize()
+    b.close()
+
+
+def test_serving_batch_runs_and_reports(bh):
+    """The 512-request serving mix at reduced resolution (sizes / 8): every
+    pixel is written, and per-request completion times are recorded."""
+    import torch
+    frames = inputs.serving_batch(512, sizes=(16, 32, 64, 128, 256))
+    b = bh.Batch(frames, bh.options(precision=bh.FP32), use_graph=True)
+    b.launch()
+    st = b.stats()
+    assert st["requests"] == 512 and st["mrays_per_s"] > 0
+    for img in b.images[:64]:
+        a = img.cpu().numpy()
+        assert np.all(a[..., 3] == 1.0)
+    b.close()
+
+
+def test_autotune_returns_a_candidate(bh, tmp_path):
+    from paper_2507_16165_amd import autotune
+    frames = mixed_frames()
+    path = tmp_path / "tune.json"
+    best = autotune.tune_batch(frames, bh.FP32, "mixed_small", cache_path=str(path), reps=1)
+    assert best["chunk"] in autotune.CHUNKS and best["grid_blocks"] > 0
+    cached = json.loads(path.read_text())
+    assert list(cached.values())[0] == best
+    # the cached entry is reused
+    assert autotune.tune_batch(frames, bh.FP32, "mixed_small", cache_path=str(path)) == best
