@@ -106,11 +106,14 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
     }
     if (n > ws.cap || ws.base == nullptr) {
         int64_t cap = n > 4096 ? n : 4096;
-        // per ray: u0 (8 B), rec, res, q64rec (16 B each), clst, q64 (4 B each), path (1 B)
+        // per ray: u0 (8 B), rec, res, q64rec (16 B each), clst, q64 (4 B each), path (1 B);
+        // the surrogate list (qsurrec 16 B, qsur 4 B) has kSlices * sur_slice_cap entries
+        const int64_t scap = bh::kSlices * bh::sur_slice_cap(cap);
         const size_t sz16 = align256((size_t)cap * 16), sz8 = align256((size_t)cap * 8),
                      sz4 = align256((size_t)cap * 4), sz1 = align256((size_t)cap);
+        const size_t szs16 = align256((size_t)scap * 16), szs4 = align256((size_t)scap * 4);
         const size_t szc = align256(sizeof(int32_t) * bh::kCtrInts);
-        const size_t total = 4 * sz16 + sz8 + 2 * sz4 + sz1 + szc + 256;
+        const size_t total = 3 * sz16 + szs16 + sz8 + 2 * sz4 + szs4 + sz1 + szc + 256;
         if (ws.base) {
             e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -130,7 +133,8 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
         ws.w.rec = (double2*)c; c += sz16;
         ws.w.res = (double2*)c; c += sz16;
         ws.w.q64rec = (double2*)c; c += sz16;
-        ws.w.sur = (double2*)c; c += sz16;
+        ws.w.qsurrec = (double2*)c; c += szs16;
+        ws.w.qsur = (int32_t*)c; c += szs4;
         ws.w.u0 = (double*)c; c += sz8;
         ws.w.clst = (int32_t*)c; c += sz4;
         ws.w.q64 = (int32_t*)c; c += sz4;
@@ -490,7 +494,8 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     b->w.path = (uint8_t*)c; c += sz1;
     b->w.ctr = (int32_t*)c; c += szc;
     b->w.u0 = nullptr;
-    b->w.sur = nullptr;
+    b->w.qsur = nullptr;
+    b->w.qsurrec = nullptr;
     int64_t* d_off = (int64_t*)c; c += align256(sizeof(int64_t) * (n + 1));
     bh::ReqDev* d_req = (bh::ReqDev*)c; c += align256(sizeof(bh::ReqDev) * n);
     bh::BatchConst* d_bc = (bh::BatchConst*)c; c += align256(sizeof(bh::BatchConst) * n);

@@ -109,14 +109,18 @@ __device__ __forceinline__ double nan_d() { return __builtin_nan(""); }
 
 // Set-up of ray i (index into the per-ray workspace) with origin o and
 // direction dv: plane reduction, impact parameter, first disk-plane crossing,
-// routing.  Returns whether the ray joins the FP64 band queue.
-__device__ __forceinline__ bool setup_ray(const double o[3], const double dv[3], const DevScene& sc,
-                                          const DevRoute& rt, int64_t i, const Work& w,
-                                          double* out_b, double& w0, double& phi1) {
-    bool to_q64 = false;
+// routing.  Returns the queue the ray joins besides the main one: kToBand
+// (FP64 band queue), kToSur (surrogate list) or kToNone.
+constexpr int kToNone = 0, kToBand = 1, kToSur = 2;
+
+__device__ __forceinline__ int setup_ray(const double o[3], const double dv[3], const DevScene& sc,
+                                         const DevRoute& rt, int64_t i, const Work& w,
+                                         double* out_b, double& b, double& w0, double& phi1) {
+    int to = kToNone;
     const Basis B = plane_basis(o, dv, sc.M, sc.r_sky);
     uint8_t path = PATH_NONE, cls = INVALID;
-    double phi_end = 0.0, b = 0.0;
+    double phi_end = 0.0;
+    b = 0.0;
     w0 = 0.0;
     phi1 = 0.0;
     if (B.ok && B.radial) {
@@ -150,10 +154,10 @@ __device__ __forceinline__ bool setup_ray(const double o[3], const double dv[3],
             cls = CAPTURED;  // below the potential peak: falls in, no disk to hit
         } else if (sur) {
             path = PATH_SUR;
-            w.sur[i] = make_double2(b, w0);
+            to = kToSur;
         } else if (rt.precision == 1 && fabs(b - bc) < rt.band) {
             path = PATH_FP64;
-            to_q64 = true;
+            to = kToBand;
         } else {
             path = rt.precision == 1 ? PATH_FP32 : PATH_FP64;
         }
@@ -161,14 +165,14 @@ __device__ __forceinline__ bool setup_ray(const double o[3], const double dv[3],
     w.path[i] = path;
     // The main queue is the index range itself; its record marks rays that
     // belong to another path (band, surrogate, set-up only) with w0 = NaN.
-    const bool main = path != PATH_NONE && path != PATH_SUR && !to_q64;
+    const bool main = path != PATH_NONE && to == kToNone;
     w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
     if (path == PATH_NONE) {
         w.res[i] = make_double2(phi_end, 0.0);
         w.clst[i] = cls;
     }
     if (out_b) out_b[i] = b;
-    return to_q64;
+    return to;
 }
 
 // Wave-aggregated append to the FP64 band queue: one atomic per wavefront
@@ -189,17 +193,38 @@ __device__ __forceinline__ void append_band(bool to_q64, int64_t i, double w0, d
     }
 }
 
+// Wave-aggregated append to slice (block index mod kSlices) of the surrogate
+// list: one atomic per wavefront that holds surrogate rays, spread over
+// kSlices counters.
+__device__ __forceinline__ void append_sur(bool to_sur, int64_t i, double b, double w0,
+                                           int64_t n, const Work& w) {
+    const uint64_t m = __ballot(to_sur);
+    if (m) {
+        const int slice = (int)(blockIdx.x % (unsigned)kSlices);
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(&w.ctr[kCtrSur + slice * kCtrStride], __popcll(m));
+        base = __shfl(base, leader);
+        if (to_sur) {
+            const int64_t slot = slice * sur_slice_cap(n) + base + rank_in(m);
+            w.qsur[slot] = (int32_t)i;
+            w.qsurrec[slot] = make_double2(b, w0);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRoute rt, Work w,
                                                   double* out_b) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool to_q64 = false;
-    double w0 = 0.0, phi1 = 0.0;
+    int to = kToNone;
+    double b = 0.0, w0 = 0.0, phi1 = 0.0;
     if (i < src.n) {
         double o[3], dv[3];
         source_ray(src, i, o, dv);
-        to_q64 = setup_ray(o, dv, sc, rt, i, w, out_b, w0, phi1);
+        to = setup_ray(o, dv, sc, rt, i, w, out_b, b, w0, phi1);
     }
-    append_band(to_q64, i, w0, phi1, w);
+    append_band(to == kToBand, i, w0, phi1, w);
+    if (rt.trust) append_sur(to == kToSur, i, b, w0, src.n, w);
 }
 
 // Request of batch ray g: the last r with off[r] <= g (binary search over the
@@ -225,8 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
     extern __shared__ int64_t s_off[];
     stage_offsets(b, s_off);
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool to_q64 = false;
-    double w0 = 0.0, phi1 = 0.0;
+    int to = kToNone;
+    double bi = 0.0, w0 = 0.0, phi1 = 0.0;
     if (g < b.total) {
         const int r = find_req(s_off, b.nreq, g);
         const ReqDev& q = b.req[r];
@@ -235,9 +260,9 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
         for (int k = 0; k < 3; ++k) o[k] = q.cam.pos[k];
         camera_dir(q.cam, g - s_off[r], dv);
         w.rq[g] = r;
-        to_q64 = setup_ray(o, dv, q.sc, q.rt, g, w, nullptr, w0, phi1);
+        to = setup_ray(o, dv, q.sc, q.rt, g, w, nullptr, bi, w0, phi1);  // no surrogate routing
     }
-    append_band(to_q64, g, w0, phi1, w);
+    append_band(to == kToBand, g, w0, phi1, w);
 }
 
 // ---------------------------------------------------------------------------

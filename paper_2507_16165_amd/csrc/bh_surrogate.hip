@@ -495,18 +495,18 @@ __global__ void k_labels_finish(int64_t n, uint8_t* cls_cap, double* phi) {
 }
 
 // ---------------------------------------------------------------------------
-// Render path: rays tagged PATH_SUR at set-up.  Each wavefront walks chunks of
-// the image, compacts the tagged rays of each 64-ray group into a list in LDS
-// and evaluates full tiles of 32; the exit azimuth goes straight into the
-// result record.  A ray whose capture logit disagrees with b > b_c is handed
-// back to the FP32 integrator by restoring its start record.
+// Render path: the surrogate list that set-up fills (kSlices slices of ray
+// indices with {b, w0}).  Tiles of 32 listed rays are dealt to wavefronts
+// round-robin (every tile costs the same); a wavefront loads its next tile's
+// entries before it evaluates the current one.  The exit azimuth goes straight
+// into the result record.  A ray whose capture logit disagrees with b > b_c is
+// handed back to the FP32 integrator by restoring its start record.
 // ---------------------------------------------------------------------------
 struct SurRender {
-    int64_t n;
+    int64_t slice_cap;  // entries per slice of the list
     Work w;
     float r0m;     // camera distance / M
     double inv_M;  // 1/M
-    int chunk;
 };
 
 // The render path's exit azimuth in FP32 (its error budget is 1e-4 rad):
@@ -519,9 +519,10 @@ __device__ inline float sweep1f(float b, float r0) {
     return 3.14159265f - a(1000.0f) - a(r0);
 }
 
-__device__ inline void sur_finish(const SurRender& a, int id, float bm, float y0, float y1) {
+__device__ inline void sur_finish(const SurRender& a, int id, double w0, float bm, float y0,
+                                  float y1) {
     if (!(y1 < 0.0f)) {
-        a.w.rec[id] = make_double2(a.w.sur[id].y, a.w.rec[id].y);
+        a.w.rec[id] = make_double2(w0, a.w.rec[id].y);
         a.w.path[id] = PATH_FP32;
         return;
     }
@@ -530,100 +531,89 @@ __device__ inline void sur_finish(const SurRender& a, int id, float bm, float y0
     a.w.clst[id] = 0;  // SKY, no integration steps
 }
 
-constexpr int kSurList = 128;  // per-wavefront list of pending ray indices
+// Entry of listed ray j of tile t (tile numbering runs over the slices in
+// order); lanes past the end of their slice read the slice's first entry.
+struct SurEntry {
+    int64_t slot;
+    bool valid;
+};
 
-template <int NT>
-__global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 2 : 1)))
+__device__ inline SurEntry sur_entry(const int* cnt, int64_t slice_cap, int64_t t, int lane) {
+    int s = 0;
+    int64_t first = 0;  // first tile of slice s
+#pragma unroll
+    for (int q = 0; q < kSlices - 1; ++q) {
+        const int64_t nt = (cnt[s] + 31) / 32;
+        if (t >= first + nt) {
+            first += nt;
+            ++s;
+        }
+    }
+    const int64_t j = (t - first) * 32 + lane;
+    const bool valid = j < cnt[s];
+    return {s * slice_cap + (valid ? j : 0), valid};
+}
+
+__global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void k_sur_render(const void* __restrict__ pack, SurRender a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    int cnt[kSlices];
+    int64_t tiles = 0;
+#pragma unroll
+    for (int q = 0; q < kSlices; ++q) {
+        cnt[q] = a.w.ctr[kCtrSur + q * kCtrStride];
+        tiles += (cnt[q] + 31) / 32;
+    }
+    constexpr int wpb = kInferThreads / 64;
+    if ((int64_t)blockIdx.x * wpb >= tiles) return;  // block-uniform: nothing for this block
     load_pack(pack, smem);
     const bf16* pk = reinterpret_cast<const bf16*>(smem);
     const float* pkf = reinterpret_cast<const float*>(smem + PK_BF16 * 2);
-    int* list = reinterpret_cast<int*>(smem + kPackBytes) + (threadIdx.x >> 6) * kSurList;
     const int l = threadIdx.x & 63;
     const float f2v = feature2(a.r0m);
-    int nl = 0;  // wave-uniform list length
-    int slice = (int)(blockIdx.x % (unsigned)kSlices), dry = 0;
-    int* heads = &a.w.ctr[kCtrSur];
-    // Evaluates the first min(nl, 32 NT) listed rays (NT tiles of 32).
-    auto run = [&](int cnt) {
-        int id[NT];
-        float bm[NT], f1[NT], f2[NT], y0[NT], y1[NT];
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            const int j = 32 * q + (l & 31);
-            id[q] = list[j < cnt ? j : 0];
-            bm[q] = (float)(a.w.sur[id[q]].x * a.inv_M);
-            f1[q] = feature1(bm[q]);
-            f2[q] = f2v;
-        }
-        mlp_tiles<NT>(pk, pkf, f1, f2, y0, y1);
-#pragma unroll
-        for (int q = 0; q < NT; ++q)
-            if (l < 32 && 32 * q + l < cnt) sur_finish(a, id[q], bm[q], y0[q], y1[q]);
-    };
-    for (;;) {
-        int k = 0;
-        if (l == 0) k = atomicAdd(&heads[slice * kCtrStride], 1);
-        k = __shfl(k, 0);
-        const int64_t base = ((int64_t)k * kSlices + slice) * a.chunk;
-        if (!(k >= 0 && base < a.n)) {
-            slice = slice + 1 == kSlices ? 0 : slice + 1;
-            if (++dry >= kSlices) break;
-            continue;
-        }
-        const int64_t end = min(base + a.chunk, a.n);
-        // The chunk's tags in one load per lane: lane l holds positions
-        // base + 8l .. base + 8l + 7 (chunk = 512 = 64 lanes x 8).
-        uint64_t tags = 0;
-        {
-            const int64_t p0 = base + 8 * l;
-            if (p0 + 8 <= end) {
-                tags = *reinterpret_cast<const uint64_t*>(a.w.path + p0);
-            } else {
-                for (int q = 0; q < 8; ++q)
-                    if (p0 + q < end) tags |= (uint64_t)a.w.path[p0 + q] << (8 * q);
-            }
-        }
-        for (int grp = 0; grp < 8; ++grp) {
-            // group grp = positions base + 64 grp + l, held by lane 8 grp + l/8
-            const int64_t pos = base + 64 * grp + l;
-            const uint64_t src = __shfl(tags, 8 * grp + (l >> 3));
-            const bool tagged = pos < end && ((src >> (8 * (l & 7))) & 0xff) == PATH_SUR;
-            const uint64_t m = __ballot(tagged);
-            if (tagged) list[nl + rank_in(m)] = (int)pos;
-            nl += __popcll(m);
-            __builtin_amdgcn_wave_barrier();
-            while (nl >= 32 * NT) {
-                run(32 * NT);
-                // move the remainder to the front of the list
-                const int rest = nl - 32 * NT;
-                const int mv = l < rest ? list[32 * NT + l] : 0;
-                __builtin_amdgcn_wave_barrier();
-                if (l < rest) list[l] = mv;
-                __builtin_amdgcn_wave_barrier();
-                nl = rest;
-            }
-        }
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    int64_t t = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    SurEntry e{0, false};
+    int id = 0;
+    double2 rec = make_double2(10.0, 0.0);
+    if (t < tiles) {
+        e = sur_entry(cnt, a.slice_cap, t, l & 31);
+        id = a.w.qsur[e.slot];
+        rec = a.w.qsurrec[e.slot];
     }
-    if (nl > 0) run(nl);  // partial last pair of tiles
+    for (; t < tiles; t += nw) {
+        // next tile's entries in flight while this one is evaluated
+        SurEntry en{0, false};
+        int idn = 0;
+        double2 recn = make_double2(10.0, 0.0);
+        if (t + nw < tiles) {
+            en = sur_entry(cnt, a.slice_cap, t + nw, l & 31);
+            idn = a.w.qsur[en.slot];
+            recn = a.w.qsurrec[en.slot];
+        }
+        const float bm = (float)(rec.x * a.inv_M);
+        float f1 = feature1(bm), f2 = f2v, y0, y1;
+        mlp_tiles<1>(pk, pkf, &f1, &f2, &y0, &y1);
+        if (l < 32 && e.valid) sur_finish(a, id, rec.y, bm, y0, y1);
+        e = en;
+        id = idn;
+        rec = recn;
+    }
 }
 
 hipError_t launch_surrogate_render(int64_t n, const Work& w, const void* pack, double M,
                                    double r_cam, int cus, hipStream_t s) {
     SurRender a;
-    a.n = n;
+    a.slice_cap = sur_slice_cap(n);
     a.w = w;
     a.r0m = (float)(r_cam / M);
     a.inv_M = 1.0 / M;
-    a.chunk = 512;  // = 64 lanes x 8 tags: one 8-byte tag load per lane per chunk
-    const size_t lds = kPackBytes + (kInferThreads / 64) * kSurList * sizeof(int);
+    // Two blocks per CU (the weights fill ~66 KB of LDS per block); blocks
+    // beyond the list's tiles return at once.
     int64_t g = (int64_t)cus * 2;
-    const int64_t need = (n + 511) / 512;
+    const int64_t need = (n + 32 * (kInferThreads / 64) - 1) / (32 * (kInferThreads / 64));
     if (g > need) g = need > 0 ? need : 1;
-    // One tile per evaluation at two wavefronts per SIMD measured faster than
-    // two tiles sharing each weight read at one wavefront per SIMD.
-    k_sur_render<1><<<(unsigned)g, kInferThreads, lds, s>>>(pack, a);
+    k_sur_render<<<(unsigned)g, kInferThreads, kPackBytes, s>>>(pack, a);
     return hipGetLastError();
 }
 
