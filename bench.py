@@ -6,11 +6,15 @@ camera at U[20, 100] M, inclination U[0, 90] deg, disk 6-30 M, checker sky at
 1000 M, FOV 60 deg; seeded).  One step = render all 16 frames through the
 whole path (set-up/routing, FP32 integration with the FP64 critical band,
 shading into resident fp32 RGBA buffers).  Value = rays per second of the
-step.  Also reported: the plain FP64 kernel on the same frames, the roofline
-of the dominant kernel (the integrator, timed with HIP events on its launch
-stream), and the CPU FP64 oracle timed on a bounded sample.
+step.  Also reported: the plain FP64 kernel on the same frames; the same
+frames with the surrogate network (trained here on the GPU first); the
+512-request batched-serving mix in one graph-replayed launch; the roofline of
+the dominant kernel (the integrator, timed with HIP events on its launch
+stream) and of the surrogate's inference kernel; and the CPU FP64 oracle
+timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-surrogate] [--no-batch] [--fp64-steps K64]
 """
 from __future__ import annotations
 
@@ -27,7 +31,8 @@ sys.path.insert(0, ROOT)
 FLOP_PER_STEP = 139          # algorithmic FLOP per Dormand-Prince step evaluation (FMA = 2)
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (scalar FP32 or FP64 FMA)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_orbit4k_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2507_16165_amd", "csrc", "bh_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2507_16165_amd", "csrc", f)
+               for f in ("bh_kernels.hip", "bh_internal.h")]
 
 
 def log(*a):
@@ -35,7 +40,13 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the integrator's sources (the traffic figure is only valid for
+    the kernel it was counted on)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
@@ -65,6 +76,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-row-stride", type=int, default=16)
     ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate leg (training and the surrogate render)")
+    ap.add_argument("--sur-epochs", type=int, default=40)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving leg")
+    ap.add_argument("--batch-requests", type=int, default=512)
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -194,15 +211,129 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
             "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "algorithmic_bytes_per_launch": 36 * W * H,
             "flop_per_launch": flop_launch,
             "avg_launch_ms": round(avg_launch_ms, 4),
         },
     }
 
+    if not args.no_surrogate:
+        line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value, step)
+    if not args.no_batch:
+        line["batch_serving"] = batch_leg(args, api, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(frames, args.cpu_row_stride, bufs, opt_fast, api, torch)
     print(json.dumps(line), flush=True)
     return 0
+
+
+FLOP_PER_SUR_RAY = 66560     # 2 x (2*128 + 128*128 + 128*128 + 128*2) multiply-adds
+PEAK_BF16_TFLOPS = 2500.0    # dense BF16 matrix-core peak
+
+
+def surrogate_leg(args, frames, bufs, api, torch, value_fast, step):
+    """Trains the network on the GPU (4M escape-side + 1M capture-side FP64
+    labels, Adam), builds its trust map, then renders the same frames with
+    FP32 + band + surrogate.  Reports the throughput, the gain over the
+    integrator alone, the share of rays the network served, its exit error
+    against the FP64 integrator on those rays, and the inference kernel's
+    matrix-core roofline."""
+    from paper_2507_16165_amd import surrogate as S
+
+    log(f"surrogate: labels + training ({args.sur_epochs} epochs)")
+    t0 = time.perf_counter()
+    sur, rep = S.fit(n_escape=4_000_000, n_capture=1_000_000, n_val=1_000_000,
+                     epochs=args.sur_epochs,
+                     log=lambda m: log(m) if m.startswith("epoch") and
+                     m.split()[1].split("/")[0] in ("1", str(args.sur_epochs)) else None)
+    fit_s = time.perf_counter() - t0
+    opt = api.options(precision=api.FP32)
+    opt.surrogate = sur.handle
+    for _ in range(args.warmup):
+        step(opt)
+    torch.cuda.synchronize()
+    api.timing_enable(True)
+    api.timing_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(opt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    tim = api.timing_read()
+    api.timing_enable(False)
+    W, H = frames[0].camera.width, frames[0].camera.height
+    rays = W * H * len(frames)
+    # share and exit error of the surrogate-served rays against the FP64 integrator
+    n_sur = 0
+    max_err = 0.0
+    opt64 = api.options(precision=api.FP64)
+    for f, buf in zip(frames, bufs):
+        _, o = api.render(f.camera, f.scene, opt, rgba=buf, fields=("cls", "exit_dir", "path"))
+        _, o64 = api.render(f.camera, f.scene, opt64, rgba=buf, fields=("cls", "exit_dir"))
+        on = o["path"] == api.PATH_SURROGATE
+        n_sur += int(on.sum().item())
+        if bool(on.any()):
+            a, b = o["exit_dir"][on], o64["exit_dir"][on]
+            ang = torch.atan2(torch.linalg.cross(a, b).norm(dim=1), (a * b).sum(1))
+            max_err = max(max_err, float(ang.max().item()))
+    sur_ms, sur_n = tim.get("surrogate", (0.0, 0))
+    sur_rays_launch = n_sur / len(frames)
+    ach = (sur_rays_launch * FLOP_PER_SUR_RAY / (sur_ms / sur_n * 1e-3) / 1e12) if sur_n else 0.0
+    value = rays / (ms * 1e-3) / 1e6
+    sur.close()
+    return {
+        "value": round(value, 2), "unit": "Mrays/s", "ms_per_step": round(ms, 4),
+        "gain_vs_fp32_band": round(value / value_fast, 4),
+        "share": round(n_sur / rays, 4),
+        "max_exit_err_rad_vs_fp64": max_err,
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
+        "fit": {"seconds": round(fit_s, 1), "train_samples": rep["train_samples"],
+                "epochs": rep["epochs"], "final_loss": rep["final_loss"],
+                "trusted_bins": rep["trusted_bins"],
+                "val_p99_err_b30_100": rep["val"].get("p99_err_b30_100"),
+                "val_p99_err_b100_1000": rep["val"].get("p99_err_b100_1000"),
+                "capture_agreement": rep["val"]["capture_agreement"]},
+        "roofline": {"kernel": "bh::k_sur_render", "bound": "mfma", "achieved": round(ach, 2),
+                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / PEAK_BF16_TFLOPS, 4),
+                     "flop_per_launch": sur_rays_launch * FLOP_PER_SUR_RAY,
+                     "avg_launch_ms": round(sur_ms / sur_n, 4) if sur_n else None},
+    }
+
+
+def batch_leg(args, api, torch):
+    """The serving mix: 512 seeded requests (square sizes 128..2048, half with
+    a disk) traced in one persistent FP32 + band launch replayed from a
+    captured hipGraph, at the autotuned launch shape.  Reports aggregate
+    rays/s and per-request completion latency (device clock, from the start
+    of the launch)."""
+    from paper_2507_16165_amd import autotune, inputs
+
+    frames = inputs.serving_batch(args.batch_requests)
+    log(f"batch: {len(frames)} requests, {sum(f.camera.pixels for f in frames)} rays; autotune")
+    cache = os.path.join(ROOT, "_build", "autotune.json")
+    best = autotune.tune_batch(frames, api.FP32, f"serving_{len(frames)}", cache_path=cache,
+                               reps=1)
+    opt = api.options(precision=api.FP32, grid_blocks=best["grid_blocks"], chunk=best["chunk"])
+    b = api.Batch(frames, opt, use_graph=True)
+    b.launch()
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        b.launch()
+        runs.append(b.stats())
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.batch_reps
+    med = sorted(runs, key=lambda r: r["makespan_ms"])[len(runs) // 2]
+    b.close()
+    return {"requests": med["requests"], "rays": med["rays"], "graph": True,
+            "grid_blocks": best["grid_blocks"], "chunk": best["chunk"],
+            "mrays_per_s": round(med["mrays_per_s"], 2), "makespan_ms": round(med["makespan_ms"], 3),
+            "p50_ms": round(med["p50_ms"], 3), "p99_ms": round(med["p99_ms"], 3),
+            "min_ms": round(med["min_ms"], 3), "wall_ms_per_launch": round(wall_ms, 3),
+            "reps": args.batch_reps}
 
 
 def cpu_baseline(frames, stride, bufs, opt_fast, api, torch):
