@@ -192,6 +192,7 @@ bh::DevScene dev_scene(const bh_scene* sc) {
     d.urin = sc->has_disk ? 1.0 / sc->disk_rin : 0.0;
     d.urout = sc->has_disk ? 1.0 / sc->disk_rout : 0.0;
     d.cell_rad = sc->checker_deg * kPi / 180.0;
+    d.inv_cell = 1.0 / d.cell_rad;
     return d;
 }
 
@@ -270,6 +271,14 @@ bh::DevCam make_cam(const bh_camera* cam) {
     c.tan_half = tan(0.5 * cam->fov_deg * kPi / 180.0);
     c.W = cam->width;
     c.H = cam->height;
+    // Pixel-centre coordinates on the image plane at unit distance (vertical
+    // field of view, square pixels): x = (2 (px + 1/2) / W - 1) t W / H and
+    // y = (1 - 2 (py + 1/2) / H) t, written as (px + 1/2) ax + bx and
+    // t - (py + 1/2) ax with ax = 2 t / H, bx = -t W / H.
+    c.ax = 2.0 * c.tan_half / cam->height;
+    c.bx = -c.tan_half * cam->width / cam->height;
+    c.r0 = sqrt(c.pos[0] * c.pos[0] + c.pos[1] * c.pos[1] + c.pos[2] * c.pos[2]);
+    for (int k = 0; k < 3; ++k) c.e1[k] = c.pos[k] / c.r0;
     return c;
 }
 
@@ -312,7 +321,7 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "integrate");
     t = timing_begin(2, stream);
-    e = bh::launch_shade(src, sc, w, rgba, dev_out(out), stream);
+    e = bh::launch_shade(src, sc, w, rgba, dev_out(out), opt->precision, stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "shade");
     ws->last_n = src.n;

@@ -52,6 +52,7 @@ struct DevScene {
     double rin, rout, power;
     double urin, urout;       // 1/rin, 1/rout: the disk test runs on u = 1/r
     double cell_rad;          // checker cell in radians
+    double inv_cell;          // 1 / cell_rad
     int has_disk;
 };
 
@@ -70,6 +71,8 @@ struct DevCam {
     double pos[3];            // camera position C
     double fwd[3], right[3], up[3];
     double tan_half;          // tan(vfov/2)
+    double e1[3], r0;         // C / |C| and |C| (first basis vector of every ray's plane)
+    double ax, bx;            // image-plane x of pixel column px: (px + 1/2) ax + bx
     int W, H;
 };
 
@@ -170,7 +173,7 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
                             const DevTol& tol, int precision, const Work& w, int cus,
                             int grid_blocks, int chunk, hipStream_t s);
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
-                        const Out& out, hipStream_t s);
+                        const Out& out, int precision, hipStream_t s);
 // Surrogate (bh_surrogate.hip): the device trust map (NULL until built) and
 // inference pack of a handle, and the render-path kernel over PATH_SUR rays.
 const uint8_t* surrogate_trust(const bh_surrogate* s);

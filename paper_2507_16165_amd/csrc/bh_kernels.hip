@@ -33,54 +33,89 @@ struct Basis {
     bool radial, ok;
 };
 
-__device__ __forceinline__ void camera_dir(const DevCam& cam, int64_t i, double d[3]) {
-    const int px = (int)(i % cam.W), py = (int)(i / cam.W);
-    const double W = cam.W, H = cam.H;
-    const double x = (2.0 * (px + 0.5) / W - 1.0) * cam.tan_half * W / H;
-    const double y = (1.0 - 2.0 * (py + 0.5) / H) * cam.tan_half;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) d[k] = cam.fwd[k] + x * cam.right[k] + y * cam.up[k];
+// 1/sqrt(x): for 1e-250 < x < 1e250 the hardware estimate refined by two
+// Newton steps r <- r + r (1 - x r^2) / 2 (each squares the relative error;
+// the result is within a few ulp); elsewhere IEEE sqrt and division.
+__device__ __forceinline__ double rsqrt_d(double x) {
+    if (!(x > 1e-250 && x < 1e250)) return 1.0 / sqrt(x);
+    double r = __builtin_amdgcn_rsq(x);
+    r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+    r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+    return r;
 }
 
-__device__ __forceinline__ Basis plane_basis(const double o[3], const double dv[3], double M,
-                                             double r_sky) {
+// Unit direction of pixel i (row-major, row 0 at the top) through the pixel
+// centre; the image-plane coordinates come from per-frame constants.
+__device__ __forceinline__ void camera_dir(const DevCam& cam, int64_t i, double d[3]) {
+    const uint32_t ii = (uint32_t)i, Wu = (uint32_t)cam.W;  // i < 2^31
+    const uint32_t py = ii / Wu, px = ii - py * Wu;
+    const double x = fma((double)px + 0.5, cam.ax, cam.bx);
+    const double y = fma(-((double)py + 0.5), cam.ax, cam.tan_half);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = fma(y, cam.up[k], fma(x, cam.right[k], cam.fwd[k]));
+}
+
+// Plane of a ray from r0 e1 with direction dv (any length): c and s are the
+// cosine and sine of the angle between dv and e1, and e2 the unit part of dv
+// orthogonal to e1 (zero for a radial ray).
+__device__ __forceinline__ Basis basis_from(const double e1[3], double r0, bool ok,
+                                            const double dv[3], double M, double r_sky) {
     Basis B;
-    B.ok = isfinite(o[0]) && isfinite(o[1]) && isfinite(o[2]) && isfinite(dv[0]) &&
-           isfinite(dv[1]) && isfinite(dv[2]);
-    const double r0 = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
-    const double dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    B.ok = B.ok && (r0 > 3.0 * M) && (r0 < r_sky) && (dn > 0.0);
+    const double dn2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+    B.ok = ok && isfinite(dn2) && (r0 > 3.0 * M) && (r0 < r_sky) && (dn2 > 0.0);
     B.r0 = r0;
-    const double ir = 1.0 / r0, id = 1.0 / dn;
+    const double id = B.ok ? rsqrt_d(dn2) : 0.0;
     double d[3], v[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        B.e1[k] = o[k] * ir;
+        B.e1[k] = e1[k];
         d[k] = dv[k] * id;
     }
-    B.c = d[0] * B.e1[0] + d[1] * B.e1[1] + d[2] * B.e1[2];
+    B.c = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = d[k] - B.c * B.e1[k];
-    B.s = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    B.radial = !(B.s > 1e-15);
-    const double is = B.radial ? 0.0 : 1.0 / B.s;
+    for (int k = 0; k < 3; ++k) v[k] = d[k] - B.c * e1[k];
+    const double s2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    B.radial = !(s2 > 1e-30);  // sin < 1e-15
+    const double is = B.radial ? 0.0 : rsqrt_d(s2);
+    B.s = s2 * is;
 #pragma unroll
     for (int k = 0; k < 3; ++k) B.e2[k] = v[k] * is;
     return B;
 }
 
-__device__ __forceinline__ void source_ray(const Source& src, int64_t i, double o[3], double d[3]) {
+// Plane of a ray with explicit origin o and direction dv.
+__device__ __forceinline__ Basis plane_basis(const double o[3], const double dv[3], double M,
+                                             double r_sky) {
+    const double ro2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+    const bool ok = isfinite(ro2) && ro2 > 0.0;
+    const double ir = ok ? rsqrt_d(ro2) : 0.0;
+    const double e1[3] = {o[0] * ir, o[1] * ir, o[2] * ir};
+    return basis_from(e1, ro2 * ir, ok, dv, M, r_sky);
+}
+
+// Plane of ray i of a source (camera pixel, or explicit origin/direction);
+// set-up and shading both call this, so they see the same basis bit for bit.
+__device__ __forceinline__ Basis source_basis(const Source& src, int64_t i, double M,
+                                              double r_sky) {
+    double dv[3];
     if (src.origin) {
+        double o[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             o[k] = src.origin[3 * i + k];
-            d[k] = src.dir[3 * i + k];
+            dv[k] = src.dir[3 * i + k];
         }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) o[k] = src.cam.pos[k];
-        camera_dir(src.cam, i, d);
+        return plane_basis(o, dv, M, r_sky);
     }
+    camera_dir(src.cam, i, dv);
+    return basis_from(src.cam.e1, src.cam.r0, true, dv, M, r_sky);
+}
+
+__device__ __forceinline__ Basis camera_basis(const DevCam& cam, int64_t i, double M,
+                                              double r_sky) {
+    double dv[3];
+    camera_dir(cam, i, dv);
+    return basis_from(cam.e1, cam.r0, true, dv, M, r_sky);
 }
 
 // First root in (0, pi] of e1z cos(phi) + e2z sin(phi) = 0; +inf if the
@@ -90,6 +125,16 @@ __device__ __forceinline__ double first_crossing(double a, double bz) {
     if (a == 0.0) return kPi;
     if (bz == 0.0) return 0.5 * kPi;
     double p = atan(-a / bz);
+    if (p <= 0.0) p += kPi;
+    return p;
+}
+
+// The same root to FP32 accuracy (the FP32 integrator's), a few ulp of atanf.
+__device__ __forceinline__ double first_crossing32(double a, double bz) {
+    if (!(a * a + bz * bz > 1e-30)) return __builtin_inf();
+    if (a == 0.0) return kPi;
+    if (bz == 0.0) return 0.5 * kPi;
+    double p = (double)atanf(__fdividef((float)-a, (float)bz));
     if (p <= 0.0) p += kPi;
     return p;
 }
@@ -113,11 +158,10 @@ __device__ __forceinline__ double nan_d() { return __builtin_nan(""); }
 // (FP64 band queue), kToSur (surrogate list) or kToNone.
 constexpr int kToNone = 0, kToBand = 1, kToSur = 2;
 
-__device__ __forceinline__ int setup_ray(const double o[3], const double dv[3], const DevScene& sc,
-                                         const DevRoute& rt, int64_t i, const Work& w,
-                                         double* out_b, double& b, double& w0, double& phi1) {
+__device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, const DevRoute& rt,
+                                         int64_t i, const Work& w, double* out_b, double& b,
+                                         double& w0, double& phi1) {
     int to = kToNone;
-    const Basis B = plane_basis(o, dv, sc.M, sc.r_sky);
     uint8_t path = PATH_NONE, cls = INVALID;
     double phi_end = 0.0;
     b = 0.0;
@@ -140,7 +184,6 @@ __device__ __forceinline__ int setup_ray(const double o[3], const double dv[3], 
         b = 1.0 / sqrt(E0);
         const double bc = kBcrit * sc.M;
         if (w.u0) w.u0[i] = u0;
-        phi1 = sc.has_disk ? first_crossing(B.e1[2], B.e2[2]) : __builtin_inf();
         // Surrogate: ingoing rays above the band whose periapsis lies outside
         // the disk (u_out^2 - 2 M u_out^3 > 1/b^2: the ray turns before
         // reaching r_out), in a bin the trust map accepts.
@@ -160,6 +203,14 @@ __device__ __forceinline__ int setup_ray(const double o[3], const double dv[3], 
             to = kToBand;
         } else {
             path = rt.precision == 1 ? PATH_FP32 : PATH_FP64;
+        }
+        // First disk-plane crossing: FP32 accuracy for the FP32 integrator,
+        // FP64 for the FP64 paths (FP64 mode and the band).
+        if (sc.has_disk) {
+            phi1 = (rt.precision == 1 && to != kToBand) ? first_crossing32(B.e1[2], B.e2[2])
+                                                        : first_crossing(B.e1[2], B.e2[2]);
+        } else {
+            phi1 = __builtin_inf();
         }
     }
     w.path[i] = path;
@@ -218,11 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int to = kToNone;
     double b = 0.0, w0 = 0.0, phi1 = 0.0;
-    if (i < src.n) {
-        double o[3], dv[3];
-        source_ray(src, i, o, dv);
-        to = setup_ray(o, dv, sc, rt, i, w, out_b, b, w0, phi1);
-    }
+    if (i < src.n) to = setup_ray(source_basis(src, i, sc.M, sc.r_sky), sc, rt, i, w, out_b, b, w0, phi1);
     append_band(to == kToBand, i, w0, phi1, w);
     if (rt.trust) append_sur(to == kToSur, i, b, w0, src.n, w);
 }
@@ -255,12 +302,9 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
     if (g < b.total) {
         const int r = find_req(s_off, b.nreq, g);
         const ReqDev& q = b.req[r];
-        double o[3], dv[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) o[k] = q.cam.pos[k];
-        camera_dir(q.cam, g - s_off[r], dv);
         w.rq[g] = r;
-        to = setup_ray(o, dv, q.sc, q.rt, g, w, nullptr, bi, w0, phi1);  // no surrogate routing
+        to = setup_ray(camera_basis(q.cam, g - s_off[r], q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
+                       nullptr, bi, w0, phi1);  // no surrogate routing
     }
     append_band(to == kToBand, g, w0, phi1, w);
 }
@@ -601,40 +645,61 @@ k_integrate_fp32(IntegArgs a, int band_blocks) {
 // ---------------------------------------------------------------------------
 // Shading and output.
 // ---------------------------------------------------------------------------
-// End vector and colour of workspace ray i with origin o and direction dv;
-// px (may be NULL) receives the RGBA value, out[oi] the per-ray record.
-__device__ __forceinline__ void shade_ray(const double o[3], const double dv[3],
-                                          const DevScene& sc, const Work& w, int64_t i,
-                                          float4* px_out, const Out& out, int64_t oi) {
-    const Basis B = plane_basis(o, dv, sc.M, sc.r_sky);
+// End vector and colour of workspace ray i with plane basis B; px (may be
+// NULL) receives the RGBA value, out[oi] the per-ray record.  F32: the FP32
+// path's rays are mapped back and shaded in FP32 (their error budget is
+// 1e-4 rad), the FP64 path's in FP64.
+template <bool F32>
+__device__ __forceinline__ void shade_ray(const Basis& B, const DevScene& sc, const Work& w,
+                                          int64_t i, float4* px_out, const Out& out, int64_t oi) {
     const int32_t cs = w.clst[i];
     const uint8_t cls = (uint8_t)(cs & 7);
     const double2 rr = w.res[i];
     const double phi = rr.x;
     const double r_hit = rr.y;
-    double sphi, cphi;
-    sincos(phi, &sphi, &cphi);
     double s[3];
+    float4 px = make_float4(0.f, 0.f, 0.f, 1.f);
+    if (F32) {
+        float sf, cf;
+        sincosf((float)phi, &sf, &cf);
+        float sv[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s[k] = cphi * B.e1[k] + sphi * B.e2[k];
-    if (cls == INVALID) s[0] = s[1] = s[2] = 0.0;
-
-    if (px_out) {
-        float4 px = make_float4(0.f, 0.f, 0.f, 1.f);
+        for (int k = 0; k < 3; ++k) sv[k] = fmaf(cf, (float)B.e1[k], sf * (float)B.e2[k]);
+        if (cls == INVALID) sv[0] = sv[1] = sv[2] = 0.0f;
+        if (cls == SKY) {
+            const float icell = (float)sc.inv_cell;
+            const float theta = atan2f(hypotf(sv[0], sv[1]), sv[2]);
+            float varphi = atan2f(sv[1], sv[0]);
+            if (varphi < 0.0f) varphi += 6.28318531f;
+            const int parity = ((int)floorf(theta * icell) + (int)floorf(varphi * icell)) & 1;
+            const float g = parity ? 0.1f : 1.0f;
+            px = make_float4(g, g, g, 1.f);
+        } else if (cls == DISK) {
+            const float I = powf((float)(r_hit / sc.rin), (float)sc.power);
+            px = make_float4(I, 0.6f * I, 0.2f * I, 1.f);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] = sv[k];
+    } else {
+        double sphi, cphi;
+        sincos(phi, &sphi, &cphi);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] = cphi * B.e1[k] + sphi * B.e2[k];
+        if (cls == INVALID) s[0] = s[1] = s[2] = 0.0;
         if (cls == SKY) {
             const double theta = atan2(hypot(s[0], s[1]), s[2]);
             double varphi = atan2(s[1], s[0]);
             if (varphi < 0.0) varphi += 2.0 * kPi;
             const long parity =
-                ((long)floor(theta / sc.cell_rad) + (long)floor(varphi / sc.cell_rad)) & 1L;
+                ((long)floor(theta * sc.inv_cell) + (long)floor(varphi * sc.inv_cell)) & 1L;
             const float g = parity ? 0.1f : 1.0f;
             px = make_float4(g, g, g, 1.f);
         } else if (cls == DISK) {
             const double I = pow(r_hit / sc.rin, sc.power);
             px = make_float4((float)I, (float)(0.6 * I), (float)(0.2 * I), 1.f);
         }
-        *px_out = px;
     }
+    if (px_out) *px_out = px;
     if (out.cls) out.cls[oi] = cls;
     if (out.phi_end) out.phi_end[oi] = phi;
     if (out.r_hit) out.r_hit[oi] = r_hit;
@@ -646,13 +711,13 @@ __device__ __forceinline__ void shade_ray(const double o[3], const double dv[3],
     }
 }
 
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work w, float* rgba,
                                                   Out out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= src.n) return;
-    double o[3], dv[3];
-    source_ray(src, i, o, dv);
-    shade_ray(o, dv, sc, w, i, rgba ? reinterpret_cast<float4*>(rgba) + i : nullptr, out, i);
+    shade_ray<F32>(source_basis(src, i, sc.M, sc.r_sky), sc, w, i,
+                   rgba ? reinterpret_cast<float4*>(rgba) + i : nullptr, out, i);
 }
 
 // Batch shading: each pixel goes to its request's image; the block that
@@ -666,11 +731,10 @@ __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
         const int r = find_req(s_off, b.nreq, g);
         const ReqDev& q = b.req[r];
         const int64_t i = g - s_off[r];
-        double o[3], dv[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) o[k] = q.cam.pos[k];
-        camera_dir(q.cam, i, dv);
-        shade_ray(o, dv, q.sc, w, g, reinterpret_cast<float4*>(q.rgba) + i, Out{}, 0);
+        const Basis B = camera_basis(q.cam, i, q.sc.M, q.sc.r_sky);
+        float4* px = reinterpret_cast<float4*>(q.rgba) + i;
+        if (q.rt.precision == 1) shade_ray<true>(B, q.sc, w, g, px, Out{}, 0);
+        else shade_ray<false>(B, q.sc, w, g, px, Out{}, 0);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -823,9 +887,10 @@ hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int
 }
 
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
-                        const Out& out, hipStream_t s) {
+                        const Out& out, int precision, hipStream_t s) {
     if (src.n == 0) return hipSuccess;
-    k_shade<<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
+    if (precision == 1) k_shade<true><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
+    else k_shade<false><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
     return hipGetLastError();
 }
 
