@@ -95,7 +95,8 @@ typedef struct {
     double atol;             /* FP64 absolute tolerance; <= 0 means rtol / r_sky        */
     double rtol_fp32;        /* FP32 integrator tolerance; atol = rtol_fp32 / r_sky     */
     double band_halfwidth;   /* FP32 mode: |b - 3 sqrt(3) M| < band_halfwidth * M -> FP64 */
-    double h0;               /* first trial step in phi                                 */
+    double h0;               /* first trial step in phi (FP64 integrator)               */
+    double h0_fp32;          /* first trial step in phi of the FP32 integrator          */
     double hmax;             /* largest step in phi                                     */
     double max_phi;          /* sweep cap -> BH_UNRESOLVED                              */
     int    max_steps;        /* cap on step attempts per ray -> BH_UNRESOLVED           */
@@ -122,7 +123,7 @@ typedef struct {
 } bh_ray_out;
 
 /* Fills defaults: FP64, rtol 1e-10, atol 0 (-> rtol/r_sky), rtol_fp32 1e-6,
- * band 0.05, h0 1e-2, hmax 1, max_phi 8 pi, max_steps 1e6, analytic capture
+ * band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps 1e6, analytic capture
  * on, auto launch shape.  Returns BH_ERR_ARG for NULL. */
 bh_status bh_default_options(bh_options* opt);
 

@@ -38,6 +38,7 @@ class Camera(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("atol", C.c_double),
                 ("rtol_fp32", C.c_double), ("band_halfwidth", C.c_double), ("h0", C.c_double),
+                ("h0_fp32", C.c_double),
                 ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
                 ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
                 ("surrogate", C.c_void_p)]

@@ -172,8 +172,9 @@ bh_status check_opt(const bh_options* o) {
     if (!isfinite(o->atol)) return fail(BH_ERR_ARG, "atol must be finite");
     if (!(isfinite(o->band_halfwidth) && o->band_halfwidth >= 0.0))
         return fail(BH_ERR_ARG, "band_halfwidth must be >= 0");
-    if (!finite_pos(o->h0) || !finite_pos(o->hmax) || !finite_pos(o->max_phi))
-        return fail(BH_ERR_ARG, "h0, hmax and max_phi must be > 0");
+    if (!finite_pos(o->h0) || !finite_pos(o->h0_fp32) || !finite_pos(o->hmax) ||
+        !finite_pos(o->max_phi))
+        return fail(BH_ERR_ARG, "h0, h0_fp32, hmax and max_phi must be > 0");
     if (o->max_steps < 1) return fail(BH_ERR_ARG, "max_steps must be >= 1");
     if (o->grid_blocks < 0 || o->chunk < 0) return fail(BH_ERR_ARG, "launch shape must be >= 0");
     if (o->chunk % 64 != 0) return fail(BH_ERR_ARG, "chunk must be a multiple of 64");
@@ -203,6 +204,7 @@ bh::DevTol dev_tol(const bh_options* o, const bh_scene* sc) {
     t.rtol32 = (float)o->rtol_fp32;
     t.atol32 = (float)(o->rtol_fp32 / sc->r_sky);
     t.h0 = o->h0;
+    t.h0_32 = o->h0_fp32;
     t.hmax = o->hmax;
     t.max_phi = o->max_phi;
     t.newton64 = 1e-15;
@@ -341,6 +343,9 @@ bh_status bh_default_options(bh_options* o) {
     o->rtol_fp32 = 1e-6;
     o->band_halfwidth = 0.05;
     o->h0 = 1e-2;
+    // The FP32 path starts near the step its tolerance allows in the far
+    // field (rtol 1e-6: ~0.2 rad) instead of ramping up from 1e-2.
+    o->h0_fp32 = 0.2;
     o->hmax = 1.0;
     o->max_phi = 8.0 * kPi;
     o->max_steps = 1000000;

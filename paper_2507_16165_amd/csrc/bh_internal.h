@@ -60,7 +60,7 @@ struct DevScene {
 struct DevTol {
     double rtol64, atol64;
     float rtol32, atol32;
-    double h0, hmax, max_phi;
+    double h0, h0_32, hmax, max_phi;  // h0_32: first step of the FP32 integrator
     double newton64;          // Newton stop on |dh| for the sky crossing
     float newton32;
     int max_steps;

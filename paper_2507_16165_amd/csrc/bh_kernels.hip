@@ -432,7 +432,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     T usky = T(a.sc.u_sky);
     T urin = T(a.sc.urin), urout = T(a.sc.urout);
     T atol = atol_in;
-    const T h0 = T(a.tol.h0), hmax = T(a.tol.hmax);
+    const T h0 = T(sizeof(T) == 4 ? a.tol.h0_32 : a.tol.h0), hmax = T(a.tol.hmax);
     const double max_phi = a.tol.max_phi;
     const int max_steps = a.tol.max_steps;
     int pf_rq = 0;
