@@ -105,6 +105,9 @@ typedef struct {
                                 effective potential peaks at b = 3 sqrt(3) M)          */
     int    grid_blocks;      /* persistent integrator grid, 256-thread blocks; 0 = auto */
     int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto  */
+    int    batch_groups;     /* batches: consecutive request groups traced one after
+                                another (1 = one launch sequence for all); 0 = auto:
+                                about 64M rays per group                             */
     const struct bh_surrogate* surrogate; /* FP32 renders only: route eligible rays to this
                                 trained network (NULL = off; see bh_surrogate_*)     */
 } bh_options;
@@ -124,7 +127,7 @@ typedef struct {
 
 /* Fills defaults: FP64, rtol 1e-10, atol 0 (-> rtol/r_sky), rtol_fp32 1e-6,
  * band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps 1e6, analytic capture
- * on, auto launch shape.  Returns BH_ERR_ARG for NULL. */
+ * on, auto launch shape and batch groups.  Returns BH_ERR_ARG for NULL. */
 bh_status bh_default_options(bh_options* opt);
 
 /* Traces n rays with world-space origins and directions (device, n*3 doubles
@@ -156,14 +159,17 @@ bh_status bh_last_counts(int64_t counts[4], void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched rendering for serving: many requests (each a camera, a scene and an
- * output image) traced together.  All requests' rays share one index space:
- * one set-up launch, ONE persistent integrator launch whose wavefronts pull
- * rays of every request from the same queue (so small and large requests
- * keep the whole chip busy), and one shading launch that records each
- * request's completion on the device clock.  With use_graph the sequence is
- * captured once into a hipGraph and each bh_batch_launch replays it.  Output
- * pixels are bit-identical to bh_render of each request with the same options.
- * The surrogate is not used in batches.
+ * output image) traced together.  The requests are split into consecutive
+ * groups of about equal ray count (bh_options.batch_groups).  Within a group
+ * all rays share one index space: one set-up launch, ONE persistent
+ * integrator launch whose wavefronts pull rays of every request of the group
+ * from the same queue (so small and large requests keep the whole chip busy),
+ * and one shading launch that records each request's completion on the
+ * device clock.  Groups run one after another, so early requests complete
+ * early.  With use_graph the whole sequence is captured once into a hipGraph
+ * and each bh_batch_launch replays it.  Output pixels are bit-identical to
+ * bh_render of each request with the same options.  The surrogate is not
+ * used in batches.
  * ------------------------------------------------------------------------- */
 typedef struct {
     bh_camera cam;

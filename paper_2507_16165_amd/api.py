@@ -41,6 +41,7 @@ class Options(C.Structure):
                 ("h0_fp32", C.c_double),
                 ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
                 ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
+                ("batch_groups", C.c_int),
                 ("surrogate", C.c_void_p)]
 
 

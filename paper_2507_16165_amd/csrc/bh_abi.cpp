@@ -176,7 +176,8 @@ bh_status check_opt(const bh_options* o) {
         !finite_pos(o->max_phi))
         return fail(BH_ERR_ARG, "h0, h0_fp32, hmax and max_phi must be > 0");
     if (o->max_steps < 1) return fail(BH_ERR_ARG, "max_steps must be >= 1");
-    if (o->grid_blocks < 0 || o->chunk < 0) return fail(BH_ERR_ARG, "launch shape must be >= 0");
+    if (o->grid_blocks < 0 || o->chunk < 0 || o->batch_groups < 0)
+        return fail(BH_ERR_ARG, "launch shape and batch groups must be >= 0");
     if (o->chunk % 64 != 0) return fail(BH_ERR_ARG, "chunk must be a multiple of 64");
     return BH_OK;
 }
@@ -429,7 +430,37 @@ struct bh_batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t last = nullptr;
     double clock_hz = 1e8;
+    // consecutive request groups: tables (offsets relative to the group's
+    // first ray) and the group's slice of the per-ray workspace
+    std::vector<bh::BatchDev> gdev;
+    std::vector<bh::Work> gw;
 };
+
+namespace {
+// Enqueues a whole batch: start stamp, then each group's sequence.
+hipError_t launch_groups(const bh_batch* b, hipStream_t s) {
+    hipError_t e = bh::launch_batch_begin(b->dev, s);
+    for (size_t g = 0; g < b->gdev.size() && e == hipSuccess; ++g)
+        e = bh::launch_batch(b->gdev[g], b->gw[g], b->tol, b->precision, b->cus, b->grid_blocks,
+                             b->chunk, s);
+    return e;
+}
+
+// Group boundaries (request indices, G+1 of them): consecutive requests with
+// about total/G rays each; G from the option, or about 64M rays per group.
+std::vector<int> make_groups(const std::vector<int64_t>& off, int option) {
+    const int n = (int)off.size() - 1;
+    const int64_t N = off[n];
+    int G = option > 0 ? option : (int)((N + (64ll << 20) - 1) / (64ll << 20));
+    if (G < 1) G = 1;
+    if (G > n) G = n;
+    std::vector<int> gr{0};
+    for (int r = 1; r < n && (int)gr.size() < G; ++r)
+        if (off[r] * G >= N * (int64_t)gr.size()) gr.push_back(r);
+    gr.push_back(n);
+    return gr;
+}
+}  // namespace
 
 extern "C" {
 
@@ -488,9 +519,15 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     const int64_t N = b->total;
     const size_t sz16 = align256((size_t)N * 16), sz4 = align256((size_t)N * 4),
                  sz1 = align256((size_t)N), szc = align256(sizeof(int32_t) * bh::kCtrInts);
+    const std::vector<int> gr = make_groups(off, opt->batch_groups);
+    const int G = (int)gr.size() - 1;
+    // per group: its requests' offsets relative to the group's first ray
+    std::vector<int64_t> goff;
+    for (int g = 0; g < G; ++g)
+        for (int r = gr[g]; r <= gr[g + 1]; ++r) goff.push_back(off[r] - off[gr[g]]);
     const size_t tables = align256(sizeof(int64_t) * (n + 1)) + align256(sizeof(bh::ReqDev) * n) +
                           align256(sizeof(bh::BatchConst) * n) + align256(8 * (size_t)n) +
-                          align256(8 * (size_t)(n + 1));
+                          align256(8 * (size_t)(n + 1)) + align256(sizeof(int64_t) * goff.size());
     const size_t total = 3 * sz16 + 3 * sz4 + sz1 + szc + tables;
     e = hipMalloc(&b->base, total);
     if (e != hipSuccess) {
@@ -514,8 +551,10 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     bh::ReqDev* d_req = (bh::ReqDev*)c; c += align256(sizeof(bh::ReqDev) * n);
     bh::BatchConst* d_bc = (bh::BatchConst*)c; c += align256(sizeof(bh::BatchConst) * n);
     unsigned long long* d_done = (unsigned long long*)c; c += align256(8 * (size_t)n);
-    unsigned long long* d_stamp = (unsigned long long*)c;
+    unsigned long long* d_stamp = (unsigned long long*)c; c += align256(8 * (size_t)(n + 1));
+    int64_t* d_goff = (int64_t*)c;
     if ((e = hipMemcpy(d_off, off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_goff, goff.data(), sizeof(int64_t) * goff.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d_req, req.data(), sizeof(bh::ReqDev) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d_bc, bc.data(), sizeof(bh::BatchConst) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(d_stamp, 0, 8 * (size_t)(n + 1))) != hipSuccess)
@@ -529,6 +568,27 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     d.done = d_done;
     d.stamp = d_stamp;
     d.req_host0 = req[0].sc;
+    for (int g = 0, k = 0; g < G; ++g) {
+        const int r0 = gr[g], ng = gr[g + 1] - gr[g];
+        const int64_t base = off[r0];
+        bh::BatchDev dg = d;
+        dg.nreq = ng;
+        dg.total = off[gr[g + 1]] - base;
+        dg.off = d_goff + k;
+        dg.req = d_req + r0;
+        dg.bconst = d_bc + r0;
+        dg.done = d_done + r0;
+        dg.stamp = d_stamp + r0;
+        k += ng + 1;
+        bh::Work wg = b->w;
+        wg.rec += base;
+        wg.res += base;
+        wg.clst += base;
+        wg.rq += base;
+        wg.path += base;
+        b->gdev.push_back(dg);
+        b->gw.push_back(wg);
+    }
     if (b->use_graph) {
         // Capture the whole sequence (counter resets are kernels, not memsets)
         // once; each launch replays it.
@@ -536,7 +596,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
             return cleanup(hip_fail(e, "capture stream"));
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess)
             return cleanup(hip_fail(e, "hipStreamBeginCapture"));
-        e = bh::launch_batch(d, b->w, b->tol, b->precision, b->cus, b->grid_blocks, b->chunk, b->cap);
+        e = launch_groups(b, b->cap);
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
         b->graph = g;
@@ -557,7 +617,7 @@ bh_status bh_batch_launch(bh_batch* b, void* stream) {
     if (b->use_graph)
         e = hipGraphLaunch(b->exec, s);
     else
-        e = bh::launch_batch(b->dev, b->w, b->tol, b->precision, b->cus, b->grid_blocks, b->chunk, s);
+        e = launch_groups(b, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     b->last = s;
     return BH_OK;

@@ -612,7 +612,7 @@ __device__ __forceinline__ const BatchConst* stage_consts(const IntegArgs& a) {
 
 // FP64 mode: one pass over all rays tagged FP64.
 template <bool BATCH>
-__global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
+__device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     run_queue<double, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
                                    a.tol.rtol64, a.tol.atol64, a.tol.newton64, bct);
@@ -623,11 +623,9 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
 // to a few hundred FP64 steps) and latency-bound; their waves start with the
 // launch and run at raised issue priority, so the FP32 waves sharing their
 // SIMDs fill the gaps and the band ends inside the FP32 work instead of
-// trailing it.  The kernel is held to 64 VGPRs (8 waves per SIMD for the FP32
-// rays); the FP64 code spills a few registers, which only band waves pay.
+// trailing it.
 template <bool BATCH>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
-k_integrate_fp32(IntegArgs a, int band_blocks) {
+__device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_blocks) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     if ((int)blockIdx.x < band_blocks) {
         __builtin_amdgcn_s_setprio(3);
@@ -640,6 +638,27 @@ k_integrate_fp32(IntegArgs a, int band_blocks) {
     }
     run_queue<float, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
                                   a.tol.rtol32, a.tol.atol32, a.tol.newton32, bct);
+}
+
+__global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
+    integrate_fp64<false>(a);
+}
+
+// Held to 64 VGPRs (8 waves per SIMD for the FP32 rays); the FP64 band code
+// spills a few registers, which only band waves pay.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
+k_integrate_fp32(IntegArgs a, int band_blocks) {
+    integrate_fp32<false>(a, band_blocks);
+}
+
+// Batch kernels: per-request constants come from LDS.
+__global__ __launch_bounds__(kBlock) void k_integrate_fp64_batch(IntegArgs a) {
+    integrate_fp64<true>(a);
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
+k_integrate_fp32_batch(IntegArgs a, int band_blocks) {
+    integrate_fp32<true>(a, band_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,28 +739,33 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
                    rgba ? reinterpret_cast<float4*>(rgba) + i : nullptr, out, i);
 }
 
-// Batch shading: each pixel goes to its request's image; the block that
-// completes a request records the device clock as the request's finish time.
+// Batch shading: each pixel goes to its request's image.  A block shades
+// chunks of kShadeChunk consecutive rays; after each chunk one thread adds the
+// chunk's pixels to the completion counter of every request it overlaps, and
+// the addition that completes a request records the device clock as its
+// finish time (one atomic per chunk and request, so the counters of large
+// requests are not contended).
+constexpr int kShadeChunk = 32 * kBlock;
+
 __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
     extern __shared__ int64_t s_off[];
     stage_offsets(b, s_off);
-    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
-    const int64_t g = g0 + threadIdx.x;
-    if (g < b.total) {
-        const int r = find_req(s_off, b.nreq, g);
-        const ReqDev& q = b.req[r];
-        const int64_t i = g - s_off[r];
-        const Basis B = camera_basis(q.cam, i, q.sc.M, q.sc.r_sky);
-        float4* px = reinterpret_cast<float4*>(q.rgba) + i;
-        if (q.rt.precision == 1) shade_ray<true>(B, q.sc, w, g, px, Out{}, 0);
-        else shade_ray<false>(B, q.sc, w, g, px, Out{}, 0);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t g1 = min(g0 + kBlock, b.total);
-        if (g0 < g1) {
-            for (int r = find_req(s_off, b.nreq, g0); r < b.nreq && s_off[r] < g1; ++r) {
-                const int64_t lo = max(g0, s_off[r]), hi = min(g1, s_off[r + 1]);
+    const int64_t nchunks = (b.total + kShadeChunk - 1) / kShadeChunk;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t c0 = c * kShadeChunk, c1 = min(c0 + kShadeChunk, b.total);
+        for (int64_t g = c0 + threadIdx.x; g < c1; g += kBlock) {
+            const int r = find_req(s_off, b.nreq, g);
+            const ReqDev& q = b.req[r];
+            const int64_t i = g - s_off[r];
+            const Basis B = camera_basis(q.cam, i, q.sc.M, q.sc.r_sky);
+            float4* px = reinterpret_cast<float4*>(q.rgba) + i;
+            if (q.rt.precision == 1) shade_ray<true>(B, q.sc, w, g, px, Out{}, 0);
+            else shade_ray<false>(B, q.sc, w, g, px, Out{}, 0);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int r = find_req(s_off, b.nreq, c0); r < b.nreq && s_off[r] < c1; ++r) {
+                const int64_t lo = max(c0, s_off[r]), hi = min(c1, s_off[r + 1]);
                 if (hi <= lo) continue;
                 const unsigned long long cnt = (unsigned long long)(hi - lo);
                 const unsigned long long total = (unsigned long long)(s_off[r + 1] - s_off[r]);
@@ -801,16 +825,15 @@ static int blocks_per_cu(K kernel, int* cache) {
     return *cache;
 }
 
+// Resident blocks per CU of a kernel with `lds` bytes of dynamic LDS (the
+// batch kernels' LDS grows with the number of requests).
 template <typename K>
-static int blocks_per_cu_lds(K kernel, size_t lds, int* cache) {
-    if (*cache == 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, lds) != hipSuccess ||
-            nb < 1)
-            nb = 1;
-        *cache = nb;
-    }
-    return *cache;
+static int blocks_per_cu_lds(K kernel, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, lds) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
 }
 
 static unsigned persistent_grid(int64_t n, int cus, int per_cu, int grid_blocks) {
@@ -837,21 +860,28 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
     a.nreq = 0;
     if (precision != 1) {
         const unsigned g =
-            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp64<false>, &occ64), grid_blocks);
-        k_integrate_fp64<false><<<g, kBlock, 0, s>>>(a);
+            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp64, &occ64), grid_blocks);
+        k_integrate_fp64<<<g, kBlock, 0, s>>>(a);
     } else {
         const unsigned g =
-            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp32<false>, &occ32), grid_blocks);
+            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp32, &occ32), grid_blocks);
         const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
-        k_integrate_fp32<false><<<g, kBlock, 0, s>>>(a, band_blocks);
+        k_integrate_fp32<<<g, kBlock, 0, s>>>(a, band_blocks);
     }
     return hipGetLastError();
 }
 
+// Batch start: clears every request's completion counter and stamps the start
+// time (b covers all requests).
+hipError_t launch_batch_begin(const BatchDev& b, hipStream_t s) {
+    k_batch_begin<<<1, 256, 0, s>>>(b);
+    return hipGetLastError();
+}
+
+// One group of a batch: b covers the group's requests (offsets relative to
+// the group's first ray) and w its rays.
 hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int precision,
                         int cus, int grid_blocks, int chunk, hipStream_t s) {
-    static int occ64 = 0, occ32 = 0;
-    k_batch_begin<<<1, 256, 0, s>>>(b);
     k_reset<<<1, 64, 0, s>>>(w.ctr);
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
     if (b.total > 0) k_setup_batch<<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
@@ -870,19 +900,21 @@ hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int
     const size_t lds_c = sizeof(BatchConst) * b.nreq;
     if (precision != 1) {
         const unsigned g =
-            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp64<true>, lds_c, &occ64),
+            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp64_batch, lds_c),
                             grid_blocks);
-        k_integrate_fp64<true><<<g, kBlock, lds_c, s>>>(a);
+        k_integrate_fp64_batch<<<g, kBlock, lds_c, s>>>(a);
     } else {
         const unsigned g =
-            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp32<true>, lds_c, &occ32),
+            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp32_batch, lds_c),
                             grid_blocks);
         const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
-        k_integrate_fp32<true><<<g, kBlock, lds_c, s>>>(a, band_blocks);
+        k_integrate_fp32_batch<<<g, kBlock, lds_c, s>>>(a, band_blocks);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_shade_batch<<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
+    int64_t gs = (b.total + kShadeChunk - 1) / kShadeChunk;
+    if (gs > (int64_t)cus * 8) gs = (int64_t)cus * 8;
+    k_shade_batch<<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
     return hipGetLastError();
 }
 

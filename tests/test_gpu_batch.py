@@ -65,6 +65,35 @@ def test_batch_equals_per_request_renders(bh, precision, graph):
     b.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_groups(bh, graph):
+    """Requests split into up to 3 consecutive groups traced one after another:
+    pixels still equal the per-request renders, every request completes, and a
+    later group's requests complete after every request of an earlier group."""
+    import torch
+    frames = mixed_frames()
+    want = _single(bh, frames, bh.FP32)
+    b = bh.Batch(frames, bh.options(precision=bh.FP32, batch_groups=3), use_graph=graph)
+    b.launch()
+    torch.cuda.synchronize()
+    for k, (img, ref) in enumerate(zip(b.images, want)):
+        np.testing.assert_array_equal(img.cpu().numpy(), ref, err_msg=f"request {k}")
+    lat = b.latencies()
+    assert np.all(lat >= 0)
+    # group boundaries: consecutive requests, about equal ray counts
+    rays = np.array([f.camera.pixels for f in frames], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(rays)])
+    bounds = [0]
+    for r in range(1, len(frames)):
+        if len(bounds) < 3 and off[r] * 3 >= off[-1] * len(bounds):
+            bounds.append(r)
+    bounds.append(len(frames))
+    assert len(bounds) >= 3  # the last request holds 46% of the rays: 2 groups here
+    for g in range(len(bounds) - 2):
+        assert lat[bounds[g]:bounds[g + 1]].max() <= lat[bounds[g + 1]:bounds[g + 2]].min()
+    b.close()
+
+
 def test_graph_replays_are_identical(bh):
     """The captured graph replayed several times, with eager work and
     synchronisation in between, reproduces the eager result every time."""
