@@ -746,21 +746,31 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
 // finish time (one atomic per chunk and request, so the counters of large
 // requests are not contended).
 constexpr int kShadeChunk = 32 * kBlock;
+static_assert(sizeof(ReqDev) % sizeof(int2) == 0, "ReqDev is copied as int2");
 
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
     extern __shared__ int64_t s_off[];
+    __shared__ ReqDev s_q;  // the chunk's request, when the chunk lies in one
     stage_offsets(b, s_off);
     const int64_t nchunks = (b.total + kShadeChunk - 1) / kShadeChunk;
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int64_t c0 = c * kShadeChunk, c1 = min(c0 + kShadeChunk, b.total);
+        const int rc = find_req(s_off, b.nreq, c0);
+        const bool one = s_off[rc + 1] >= c1;  // block-uniform
+        if (one) {
+            const int2* src = reinterpret_cast<const int2*>(b.req + rc);
+            int2* dst = reinterpret_cast<int2*>(&s_q);
+            for (int k = threadIdx.x; k < (int)(sizeof(ReqDev) / sizeof(int2)); k += kBlock)
+                dst[k] = src[k];
+            __syncthreads();
+        }
         for (int64_t g = c0 + threadIdx.x; g < c1; g += kBlock) {
-            const int r = find_req(s_off, b.nreq, g);
-            const ReqDev& q = b.req[r];
+            const int r = one ? rc : find_req(s_off, b.nreq, g);
+            const ReqDev& q = one ? s_q : b.req[r];
             const int64_t i = g - s_off[r];
             const Basis B = camera_basis(q.cam, i, q.sc.M, q.sc.r_sky);
-            float4* px = reinterpret_cast<float4*>(q.rgba) + i;
-            if (q.rt.precision == 1) shade_ray<true>(B, q.sc, w, g, px, Out{}, 0);
-            else shade_ray<false>(B, q.sc, w, g, px, Out{}, 0);
+            shade_ray<F32>(B, q.sc, w, g, reinterpret_cast<float4*>(q.rgba) + i, Out{}, 0);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -914,7 +924,8 @@ hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int
     if (e != hipSuccess) return e;
     int64_t gs = (b.total + kShadeChunk - 1) / kShadeChunk;
     if (gs > (int64_t)cus * 8) gs = (int64_t)cus * 8;
-    k_shade_batch<<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
+    if (precision == 1) k_shade_batch<true><<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
+    else k_shade_batch<false><<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
     return hipGetLastError();
 }
 
