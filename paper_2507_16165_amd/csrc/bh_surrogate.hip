@@ -90,18 +90,34 @@ struct GemmArgs {
     int64_t cf_m, cf_n;
     bf16* Cb;
     int64_t cb_m, cb_n;
+    // split-K: ksplit > 1 writes FP32 partial tiles of K/ksplit-long slices
+    // to part[ks][M][N]; k_gemm_reduce sums them in slice order (so the
+    // result does not depend on scheduling) and applies the epilogue.
+    int ksplit;
+    float* part;
 };
+
+// The epilogue of output element (i, j).
+__device__ inline void gemm_store(const GemmArgs& g, int64_t i, int64_t j, float v) {
+    if (g.bias) v += g.bias[j];
+    if (g.relu) v = fmaxf(v, 0.0f);
+    if (g.mask && !((float)g.mask[i * g.mk_m + j * g.mk_n] > 0.0f)) v = 0.0f;
+    if (g.Cf) g.Cf[i * g.cf_m + j * g.cf_n] = v;
+    if (g.Cb) g.Cb[i * g.cb_m + j * g.cb_n] = (bf16)v;
+}
 
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     const int wave = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
-    const int tiles_n = g.N >> 5;
-    if (wave >= (g.M >> 5) * tiles_n) return;  // whole wavefront
-    const int tm = wave / tiles_n, tn = wave % tiles_n;
+    const int tiles_n = g.N >> 5, tiles = (g.M >> 5) * tiles_n;
+    if (wave >= tiles * g.ksplit) return;  // whole wavefront
+    const int ks = wave / tiles, t = wave % tiles;
+    const int tm = t / tiles_n, tn = t % tiles_n;
     const int l = threadIdx.x & 63, h = l >> 5, c = l & 31;
     f32x16 acc = {};
     const int64_t arow = (int64_t)(tm * 32 + c) * g.a_m;
     const int64_t bcol = (int64_t)(tn * 32 + c) * g.b_n;
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    const int kc = g.K / g.ksplit;
+    for (int k0 = ks * kc; k0 < (ks + 1) * kc; k0 += 16) {
         bf16x8 a, b;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -114,13 +130,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t i = tm * 32 + 8 * (r >> 2) + 4 * h + (r & 3), j = tn * 32 + c;
-        float v = acc[r];
-        if (g.bias) v += g.bias[j];
-        if (g.relu) v = fmaxf(v, 0.0f);
-        if (g.mask && !((float)g.mask[i * g.mk_m + j * g.mk_n] > 0.0f)) v = 0.0f;
-        if (g.Cf) g.Cf[i * g.cf_m + j * g.cf_n] = v;
-        if (g.Cb) g.Cb[i * g.cb_m + j * g.cb_n] = (bf16)v;
+        if (g.ksplit > 1) g.part[((int64_t)ks * g.M + i) * g.N + j] = acc[r];
+        else gemm_store(g, i, j, acc[r]);
     }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g) {
+    const int64_t mn = (int64_t)g.M * g.N;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= mn) return;
+    float v = 0.0f;
+    for (int ks = 0; ks < g.ksplit; ++ks) v += g.part[ks * mn + idx];
+    gemm_store(g, idx / g.N, idx % g.N, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -643,6 +664,7 @@ struct bh_surrogate {
     float *Y = nullptr, *tgt = nullptr, *esc = nullptr, *capf = nullptr;
     float *gW1ext = nullptr, *gW4pad = nullptr, *cs = nullptr;  // cs: 3 x 32 x 128
     float* loss = nullptr;
+    float* part = nullptr;  // split-K partial products, kMaxSplit x 128 x 128
     // label scratch (grown on demand)
     void* lab = nullptr;
     int64_t lab_cap = 0;
@@ -655,9 +677,26 @@ namespace {
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+// Split-K for the weight-gradient products (K = batch, at most 128 x 128
+// outputs: too few tiles to fill the chip): slices of >= 256, at most
+// kMaxSplit of them.
+constexpr int kMaxSplit = 16;
+
+hipError_t gemm(GemmArgs g, hipStream_t s, float* part) {
     const int tiles = (g.M / 32) * (g.N / 32);
-    k_gemm<<<(tiles + 3) / 4, 256, 0, s>>>(g);
+    g.ksplit = 1;
+    g.part = part;
+    if (g.K >= 1024 && (int64_t)g.M * g.N <= kH * kH) {
+        while (g.ksplit < kMaxSplit && g.K / (2 * g.ksplit) >= 256 &&
+               (g.K / 16) % (2 * g.ksplit) == 0)
+            g.ksplit *= 2;
+    }
+    const int waves = tiles * g.ksplit;
+    k_gemm<<<(waves + 3) / 4, 256, 0, s>>>(g);
+    if (g.ksplit > 1) {
+        const int64_t mn = (int64_t)g.M * g.N;
+        k_gemm_reduce<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(g);
+    }
     return hipGetLastError();
 }
 
@@ -715,6 +754,7 @@ bh_status bh_surrogate_create(const float* params, int64_t count, int64_t max_ba
     total += al(B * 32 * 2) + 3 * al(B * kH * 2) + al(B * 32 * 2) + 3 * al(B * kH * 2) + al(B * 2);
     total += al(B * 32 * 4) + 3 * al(B * 4) + al(32 * kH * 4) + al(kH * 32 * 4) + al(3 * 32 * kH * 4) +
              256;
+    total += al((size_t)kMaxSplit * kH * kH * 4);
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, total);
     if (e != hipSuccess) {
@@ -757,6 +797,7 @@ bh_status bh_surrogate_create(const float* params, int64_t count, int64_t max_ba
     s->tgt = (float*)take(B * 4);
     s->esc = (float*)take(B * 4);
     s->capf = (float*)take(B * 4);
+    s->part = (float*)take((size_t)kMaxSplit * kH * kH * 4);
     s->gW1ext = (float*)take(32 * kH * 4);
     s->gW4pad = (float*)take(kH * 32 * 4);
     s->cs = (float*)take(3 * 32 * kH * 4);
@@ -822,47 +863,47 @@ bh_status bh_surrogate_train_step(bh_surrogate* s, const double* b, const double
     // forward
     GemmArgs g = gemm_args(s->X1, 32, 1, s->t.W1ext, kH, 1, N, kH, 32);
     g.relu = 1; g.Cb = s->H1; g.cb_m = kH; g.cb_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->H1, kH, 1, s->t.W2b, kH, 1, N, kH, kH);
     g.bias = s->t.b2r; g.relu = 1; g.Cb = s->H2; g.cb_m = kH; g.cb_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->H2, kH, 1, s->t.W3b, kH, 1, N, kH, kH);
     g.bias = s->t.b3r; g.relu = 1; g.Cb = s->H3; g.cb_m = kH; g.cb_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->H3, kH, 1, s->t.W4pad, 32, 1, N, 32, kH);
     g.bias = s->t.b4pad; g.Cf = s->Y; g.cf_m = 32; g.cf_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     k_loss<<<nb, 256, 0, st>>>(n, s->Y, s->tgt, s->esc, s->capf, s->dY, s->loss);
     HIPCHK(hipGetLastError(), "loss");
     // backward: dZ3 = (dY W4^T) * [H3 > 0]
     g = gemm_args(s->dY, 32, 1, s->t.W4pad, 1, 32, N, kH, 32);
     g.mask = s->H3; g.mk_m = kH; g.mk_n = 1; g.Cb = s->dZ3; g.cb_m = kH; g.cb_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->H3, 1, kH, s->dY, 32, 1, kH, 32, N);  // gW4pad = H3^T dY
     g.Cf = s->gW4pad; g.cf_m = 32; g.cf_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->dZ3, kH, 1, s->t.W3b, 1, kH, N, kH, kH);  // dZ2
     g.mask = s->H2; g.mk_m = kH; g.mk_n = 1; g.Cb = s->dZ2; g.cb_m = kH; g.cb_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->H2, 1, kH, s->dZ3, kH, 1, kH, kH, N);  // gW3 = H2^T dZ3
     g.Cf = s->G + OFF_W3; g.cf_m = kH; g.cf_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->dZ2, kH, 1, s->t.W2b, 1, kH, N, kH, kH);  // dZ1
     g.mask = s->H1; g.mk_m = kH; g.mk_n = 1; g.Cb = s->dZ1; g.cb_m = kH; g.cb_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->H1, 1, kH, s->dZ2, kH, 1, kH, kH, N);  // gW2 = H1^T dZ2
     g.Cf = s->G + OFF_W2; g.cf_m = kH; g.cf_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     g = gemm_args(s->X1, 1, 32, s->dZ1, kH, 1, 32, kH, N);  // gW1ext = X1^T dZ1
     g.Cf = s->gW1ext; g.cf_m = kH; g.cf_n = 1;
-    HIPCHK(gemm(g, st), "gemm");
+    HIPCHK(gemm(g, st, s->part), "gemm");
     // bias gradients: column sums through a ones operand (row 0 of the result)
     const bf16* cols[3] = {s->dZ2, s->dZ3, s->dY};
     const int ncol[3] = {kH, kH, 32};
     for (int q = 0; q < 3; ++q) {
         g = gemm_args(s->ones, 0, 1, cols[q], ncol[q], 1, 32, ncol[q], N);
         g.Cf = s->cs + q * 32 * kH; g.cf_m = ncol[q]; g.cf_n = 1;
-        HIPCHK(gemm(g, st), "gemm");
+        HIPCHK(gemm(g, st, s->part), "gemm");
     }
     k_assemble<<<1, kH, 0, st>>>(s->gW1ext, s->gW4pad, s->cs, s->cs + 32 * kH, s->cs + 2 * 32 * kH,
                                  s->G);
