@@ -80,6 +80,8 @@ def main() -> int:
                     help="skip the surrogate leg (training and the surrogate render)")
     ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving leg")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the all-pixel comparison of the fast path with the FP64 kernel")
     ap.add_argument("--batch-requests", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -218,6 +220,8 @@ def main() -> int:
         },
     }
 
+    if not args.no_accuracy:
+        line["accuracy_all_pixels"] = accuracy_leg(frames, api, torch)
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value, step)
     if not args.no_batch:
@@ -226,6 +230,91 @@ def main() -> int:
         line["cpu_baseline"] = cpu_baseline(frames, args.cpu_row_stride, bufs, opt_fast, api, torch)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def accuracy_leg(frames, api, torch):
+    """Every pixel of the 16 frames: the FP32 + band path against the FP64
+    kernel (itself held to the CPU oracle within 1e-8 rad by the parity
+    tests).  Rays in the critical band |b - 3 sqrt(3) M| < 0.05 M are the
+    ambiguity zone for the class; sky and disk rays of equal class elsewhere
+    give the exit-direction and hit-radius errors; checker-boundary pixels
+    (within 1e-4 rad of a cell edge) are left out of the colour count."""
+    import math
+    W, H = frames[0].camera.width, frames[0].camera.height
+    fields = ("cls", "b", "exit_dir", "r_hit")
+    opt32 = api.options(precision=api.FP32)
+    opt64 = api.options(precision=api.FP64)
+    img32 = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    img64 = torch.empty_like(img32)
+    n = 0
+    mism = 0
+    edge_n = 0
+    pairs = {}
+    band = 0
+    ang_max = 0.0
+    rr_max = 0.0
+    hist = torch.zeros(200, dtype=torch.float64, device="cuda")   # log10 bins of the angle
+    colour_bad = 0
+    colour_n = 0
+    log(f"accuracy: all {len(frames)} frames, FP32 + band vs FP64")
+    for f in frames:
+        _, a = api.render(f.camera, f.scene, opt32, rgba=img32, fields=fields)
+        _, b = api.render(f.camera, f.scene, opt64, rgba=img64, fields=fields)
+        M = f.scene.M
+        bc = 3.0 * math.sqrt(3.0) * M
+        in_band = (b["b"] - bc).abs() < 0.05 * M
+        same = a["cls"] == b["cls"]
+        # disk-edge zone: a DISK / non-DISK disagreement whose DISK side hit
+        # within 1e-4 r of an edge (the FP32 radius tolerance)
+        one_disk = (a["cls"] == 2) ^ (b["cls"] == 2)
+        r_d = torch.where(a["cls"] == 2, a["r_hit"], b["r_hit"])
+        rin, rout = f.scene.disk if f.scene.disk is not None else (0.0, 0.0)
+        edge_zone = one_disk & (((r_d - rin).abs() < 1e-4 * rin) | ((r_d - rout).abs() < 1e-4 * rout))
+        bad = ~same & ~in_band & ~edge_zone
+        mism += int(bad.sum().item())
+        edge_n += int((~same & ~in_band & edge_zone).sum().item())
+        for i in torch.nonzero(bad).flatten()[:8].tolist():
+            pairs[f"{int(b['cls'][i])}->{int(a['cls'][i])}"] = pairs.get(
+                f"{int(b['cls'][i])}->{int(a['cls'][i])}", 0) + 1
+        band += int(in_band.sum().item())
+        ok = same & ~in_band
+        sky = ok & (b["cls"] == 0)
+        u, v = a["exit_dir"][sky], b["exit_dir"][sky]
+        ang = torch.atan2(torch.linalg.cross(u, v).norm(dim=1), (u * v).sum(1))
+        if ang.numel():
+            ang_max = max(ang_max, float(ang.max().item()))
+            idx = ((ang.clamp_min(1e-20).log10() + 20.0) * 10.0).long().clamp(0, 199)
+            hist += torch.bincount(idx, minlength=200).double()
+        dsk = ok & (b["cls"] == 2)
+        if bool(dsk.any()):
+            rr_max = max(rr_max, float((a["r_hit"][dsk] / b["r_hit"][dsk] - 1.0).abs().max().item()))
+        # colour: checker-edge pixels (exit within 1e-4 rad of a cell boundary) are ambiguous
+        s = b["exit_dir"]
+        th = torch.atan2(torch.hypot(s[:, 0], s[:, 1]), s[:, 2])
+        ph = torch.remainder(torch.atan2(s[:, 1], s[:, 0]), 2 * math.pi)
+        cell = math.radians(f.scene.checker_deg)
+
+        def near(x):
+            fr = x / cell
+            return (fr - fr.round()).abs() * cell < 1e-4
+
+        edge = (b["cls"] == 0) & (near(th) | near(ph) | (ph < 1e-4) | (2 * math.pi - ph < 1e-4))
+        cok = ok & ~edge
+        d = (img32.view(-1, 4) - img64.view(-1, 4)).abs().amax(1)
+        tol = torch.where(b["cls"] == 2, 4e-4 * img64.view(-1, 4).abs().amax(1) + 1e-7,
+                          torch.full_like(d, 1e-6))
+        colour_bad += int(((d > tol) & cok).sum().item())
+        colour_n += int(cok.sum().item())
+        n += W * H
+    cum = torch.cumsum(hist, 0)
+    p99_bin = int(torch.searchsorted(cum, 0.99 * cum[-1]).item())
+    return {"rays": n, "reference": "FP64 kernel (rtol 1e-10)", "band_rays": band,
+            "class_mismatch_in_disk_edge_zone": edge_n,
+            "class_mismatch_outside_zones": mism, "mismatch_pairs_fp64_to_fp32": pairs,
+            "max_exit_angle_rad": ang_max,
+            "p99_exit_angle_rad_upper": 10 ** ((p99_bin + 1) / 10.0 - 20.0),
+            "max_disk_r_rel": rr_max,
+            "colour_mismatch_fraction": colour_bad / max(colour_n, 1)}
 
 
 FLOP_PER_SUR_RAY = 66560     # 2 x (2*128 + 128*128 + 128*128 + 128*2) multiply-adds
