@@ -282,6 +282,7 @@ bh::DevCam make_cam(const bh_camera* cam) {
     c.bx = -c.tan_half * cam->width / cam->height;
     c.r0 = sqrt(c.pos[0] * c.pos[0] + c.pos[1] * c.pos[1] + c.pos[2] * c.pos[2]);
     for (int k = 0; k < 3; ++k) c.e1[k] = c.pos[k] / c.r0;
+    c.u0 = 1.0 / c.r0;
     return c;
 }
 

@@ -71,7 +71,7 @@ struct DevCam {
     double pos[3];            // camera position C
     double fwd[3], right[3], up[3];
     double tan_half;          // tan(vfov/2)
-    double e1[3], r0;         // C / |C| and |C| (first basis vector of every ray's plane)
+    double e1[3], r0, u0;     // C / |C|, |C| (first basis vector of every ray's plane), 1/|C|
     double ax, bx;            // image-plane x of pixel column px: (px + 1/2) ax + bx
     int W, H;
 };

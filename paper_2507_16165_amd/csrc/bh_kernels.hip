@@ -29,7 +29,7 @@ constexpr double kBcrit = 5.19615242270663188058;  // 3 sqrt(3)
 // ---------------------------------------------------------------------------
 struct Basis {
     double e1[3], e2[3];
-    double c, s, r0;
+    double c, s, is, r0, u0;  // is = 1/s (0 for a radial ray), u0 = 1/r0
     bool radial, ok;
 };
 
@@ -58,9 +58,10 @@ __device__ __forceinline__ void camera_dir(const DevCam& cam, int64_t i, double 
 // Plane of a ray from r0 e1 with direction dv (any length): c and s are the
 // cosine and sine of the angle between dv and e1, and e2 the unit part of dv
 // orthogonal to e1 (zero for a radial ray).
-__device__ __forceinline__ Basis basis_from(const double e1[3], double r0, bool ok,
+__device__ __forceinline__ Basis basis_from(const double e1[3], double r0, double u0, bool ok,
                                             const double dv[3], double M, double r_sky) {
     Basis B;
+    B.u0 = u0;
     const double dn2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
     B.ok = ok && isfinite(dn2) && (r0 > 3.0 * M) && (r0 < r_sky) && (dn2 > 0.0);
     B.r0 = r0;
@@ -77,6 +78,7 @@ __device__ __forceinline__ Basis basis_from(const double e1[3], double r0, bool 
     const double s2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     B.radial = !(s2 > 1e-30);  // sin < 1e-15
     const double is = B.radial ? 0.0 : rsqrt_d(s2);
+    B.is = is;
     B.s = s2 * is;
 #pragma unroll
     for (int k = 0; k < 3; ++k) B.e2[k] = v[k] * is;
@@ -90,7 +92,7 @@ __device__ __forceinline__ Basis plane_basis(const double o[3], const double dv[
     const bool ok = isfinite(ro2) && ro2 > 0.0;
     const double ir = ok ? rsqrt_d(ro2) : 0.0;
     const double e1[3] = {o[0] * ir, o[1] * ir, o[2] * ir};
-    return basis_from(e1, ro2 * ir, ok, dv, M, r_sky);
+    return basis_from(e1, ro2 * ir, ir, ok, dv, M, r_sky);
 }
 
 // Plane of ray i of a source (camera pixel, or explicit origin/direction);
@@ -108,14 +110,14 @@ __device__ __forceinline__ Basis source_basis(const Source& src, int64_t i, doub
         return plane_basis(o, dv, M, r_sky);
     }
     camera_dir(src.cam, i, dv);
-    return basis_from(src.cam.e1, src.cam.r0, true, dv, M, r_sky);
+    return basis_from(src.cam.e1, src.cam.r0, src.cam.u0, true, dv, M, r_sky);
 }
 
 __device__ __forceinline__ Basis camera_basis(const DevCam& cam, int64_t i, double M,
                                               double r_sky) {
     double dv[3];
     camera_dir(cam, i, dv);
-    return basis_from(cam.e1, cam.r0, true, dv, M, r_sky);
+    return basis_from(cam.e1, cam.r0, cam.u0, true, dv, M, r_sky);
 }
 
 // First root in (0, pi] of e1z cos(phi) + e2z sin(phi) = 0; +inf if the
@@ -177,11 +179,11 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
             cls = SKY;
         }
     } else if (B.ok) {
-        const double u0 = 1.0 / B.r0;
-        w0 = -u0 * B.c / B.s;
+        const double u0 = B.u0;
+        w0 = -u0 * B.c * B.is;
         // First integral of Eq. (1): w^2 + u^2 - 2 M u^3 = 1/b^2.
         const double E0 = w0 * w0 + u0 * u0 - 2.0 * sc.M * u0 * u0 * u0;
-        b = 1.0 / sqrt(E0);
+        b = rsqrt_d(E0);
         const double bc = kBcrit * sc.M;
         if (w.u0) w.u0[i] = u0;
         // Surrogate: ingoing rays above the band whose periapsis lies outside
@@ -664,11 +666,114 @@ k_integrate_fp32_batch(IntegArgs a, int band_blocks) {
 // ---------------------------------------------------------------------------
 // Shading and output.
 // ---------------------------------------------------------------------------
-// End vector and colour of workspace ray i with plane basis B; px (may be
-// NULL) receives the RGBA value, out[oi] the per-ray record.  F32: the FP32
-// path's rays are mapped back and shaded in FP32 (their error budget is
-// 1e-4 rad), the FP64 path's in FP64.
-template <bool F32>
+// Mapping back to 3-D and shading of workspace ray i; px (may be NULL)
+// receives the RGBA value, out[oi] the per-ray record.  The FP32 path's rays
+// are mapped and shaded in FP32 (their error budget is 1e-4 rad), the FP64
+// path's in FP64.
+//
+// The FP32 path's mapping back to 3-D, all in FP32: the plane basis from the
+// float camera direction, then the exit vector and the shading.  (A ray
+// whose sin(angle to e1) is s has e2 good to ~1e-7/s; rays with s below
+// ~1e-3 fall in near the axis, where sin(phi_end) is as small.)
+struct Basis32 {
+    float e1[3], e2[3];
+};
+
+__device__ __forceinline__ Basis32 basis32(const float e1[3], const float dv[3]) {
+    Basis32 B;
+    const float dn2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+    const float id = dn2 > 0.0f ? __builtin_amdgcn_rsqf(dn2) : 0.0f;
+    float v[3];
+    float c = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        B.e1[k] = e1[k];
+        c = fmaf(dv[k] * id, e1[k], c);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = fmaf(-c, e1[k], dv[k] * id);
+    const float s2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const float is = s2 > 1e-30f ? __builtin_amdgcn_rsqf(s2) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) B.e2[k] = v[k] * is;
+    return B;
+}
+
+__device__ __forceinline__ Basis32 camera_basis32(const DevCam& cam, int64_t i) {
+    float e1[3], dv[3];
+    const uint32_t ii = (uint32_t)i, Wu = (uint32_t)cam.W;  // i < 2^31
+    const uint32_t py = ii / Wu, px = ii - py * Wu;
+    const float x = fmaf((float)px + 0.5f, (float)cam.ax, (float)cam.bx);
+    const float y = fmaf(-((float)py + 0.5f), (float)cam.ax, (float)cam.tan_half);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = (float)cam.e1[k];
+        dv[k] = fmaf(y, (float)cam.up[k], fmaf(x, (float)cam.right[k], (float)cam.fwd[k]));
+    }
+    return basis32(e1, dv);
+}
+
+__device__ __forceinline__ Basis32 source_basis32(const Source& src, int64_t i) {
+    float e1[3], dv[3];
+    if (src.origin) {
+        float o[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            o[k] = (float)src.origin[3 * i + k];
+            dv[k] = (float)src.dir[3 * i + k];
+        }
+        const float ro2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+        const float ir = ro2 > 0.0f ? __builtin_amdgcn_rsqf(ro2) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) e1[k] = o[k] * ir;
+        return basis32(e1, dv);
+    }
+    return camera_basis32(src.cam, i);
+}
+
+__device__ __forceinline__ float4 shade_px32(const Basis32& B, const DevScene& sc, uint8_t cls,
+                                             double phi, double r_hit, float sv[3]) {
+    float sf, cf;
+    sincosf((float)phi, &sf, &cf);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sv[k] = fmaf(cf, B.e1[k], sf * B.e2[k]);
+    if (cls == INVALID) sv[0] = sv[1] = sv[2] = 0.0f;
+    float4 px = make_float4(0.f, 0.f, 0.f, 1.f);
+    if (cls == SKY) {
+        const float icell = (float)sc.inv_cell;
+        const float theta = atan2f(sqrtf(fmaf(sv[0], sv[0], sv[1] * sv[1])), sv[2]);
+        float varphi = atan2f(sv[1], sv[0]);
+        if (varphi < 0.0f) varphi += 6.28318531f;
+        const int parity = ((int)floorf(theta * icell) + (int)floorf(varphi * icell)) & 1;
+        const float g = parity ? 0.1f : 1.0f;
+        px = make_float4(g, g, g, 1.f);
+    } else if (cls == DISK) {
+        const float I = powf((float)(r_hit / sc.rin), (float)sc.power);
+        px = make_float4(I, 0.6f * I, 0.2f * I, 1.f);
+    }
+    return px;
+}
+
+__device__ __forceinline__ void shade_ray32(const Basis32& B, const DevScene& sc, const Work& w,
+                                            int64_t i, float4* px_out, const Out& out,
+                                            int64_t oi) {
+    const int32_t cs = w.clst[i];
+    const uint8_t cls = (uint8_t)(cs & 7);
+    const double2 rr = w.res[i];
+    float sv[3];
+    const float4 px = shade_px32(B, sc, cls, rr.x, rr.y, sv);
+    if (px_out) *px_out = px;
+    if (out.cls) out.cls[oi] = cls;
+    if (out.phi_end) out.phi_end[oi] = rr.x;
+    if (out.r_hit) out.r_hit[oi] = rr.y;
+    if (out.steps) out.steps[oi] = cs >> 3;
+    if (out.path) out.path[oi] = w.path[i];
+    if (out.exit_dir) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out.exit_dir[3 * oi + k] = sv[k];
+    }
+}
+
 __device__ __forceinline__ void shade_ray(const Basis& B, const DevScene& sc, const Work& w,
                                           int64_t i, float4* px_out, const Out& out, int64_t oi) {
     const int32_t cs = w.clst[i];
@@ -678,45 +783,22 @@ __device__ __forceinline__ void shade_ray(const Basis& B, const DevScene& sc, co
     const double r_hit = rr.y;
     double s[3];
     float4 px = make_float4(0.f, 0.f, 0.f, 1.f);
-    if (F32) {
-        float sf, cf;
-        sincosf((float)phi, &sf, &cf);
-        float sv[3];
+    double sphi, cphi;
+    sincos(phi, &sphi, &cphi);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sv[k] = fmaf(cf, (float)B.e1[k], sf * (float)B.e2[k]);
-        if (cls == INVALID) sv[0] = sv[1] = sv[2] = 0.0f;
-        if (cls == SKY) {
-            const float icell = (float)sc.inv_cell;
-            const float theta = atan2f(hypotf(sv[0], sv[1]), sv[2]);
-            float varphi = atan2f(sv[1], sv[0]);
-            if (varphi < 0.0f) varphi += 6.28318531f;
-            const int parity = ((int)floorf(theta * icell) + (int)floorf(varphi * icell)) & 1;
-            const float g = parity ? 0.1f : 1.0f;
-            px = make_float4(g, g, g, 1.f);
-        } else if (cls == DISK) {
-            const float I = powf((float)(r_hit / sc.rin), (float)sc.power);
-            px = make_float4(I, 0.6f * I, 0.2f * I, 1.f);
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) s[k] = sv[k];
-    } else {
-        double sphi, cphi;
-        sincos(phi, &sphi, &cphi);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) s[k] = cphi * B.e1[k] + sphi * B.e2[k];
-        if (cls == INVALID) s[0] = s[1] = s[2] = 0.0;
-        if (cls == SKY) {
-            const double theta = atan2(hypot(s[0], s[1]), s[2]);
-            double varphi = atan2(s[1], s[0]);
-            if (varphi < 0.0) varphi += 2.0 * kPi;
-            const long parity =
-                ((long)floor(theta * sc.inv_cell) + (long)floor(varphi * sc.inv_cell)) & 1L;
-            const float g = parity ? 0.1f : 1.0f;
-            px = make_float4(g, g, g, 1.f);
-        } else if (cls == DISK) {
-            const double I = pow(r_hit / sc.rin, sc.power);
-            px = make_float4((float)I, (float)(0.6 * I), (float)(0.2 * I), 1.f);
-        }
+    for (int k = 0; k < 3; ++k) s[k] = cphi * B.e1[k] + sphi * B.e2[k];
+    if (cls == INVALID) s[0] = s[1] = s[2] = 0.0;
+    if (cls == SKY) {
+        const double theta = atan2(hypot(s[0], s[1]), s[2]);
+        double varphi = atan2(s[1], s[0]);
+        if (varphi < 0.0) varphi += 2.0 * kPi;
+        const long parity =
+            ((long)floor(theta * sc.inv_cell) + (long)floor(varphi * sc.inv_cell)) & 1L;
+        const float g = parity ? 0.1f : 1.0f;
+        px = make_float4(g, g, g, 1.f);
+    } else if (cls == DISK) {
+        const double I = pow(r_hit / sc.rin, sc.power);
+        px = make_float4((float)I, (float)(0.6 * I), (float)(0.2 * I), 1.f);
     }
     if (px_out) *px_out = px;
     if (out.cls) out.cls[oi] = cls;
@@ -735,8 +817,9 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
                                                   Out out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= src.n) return;
-    shade_ray<F32>(source_basis(src, i, sc.M, sc.r_sky), sc, w, i,
-                   rgba ? reinterpret_cast<float4*>(rgba) + i : nullptr, out, i);
+    float4* px = rgba ? reinterpret_cast<float4*>(rgba) + i : nullptr;
+    if (F32) shade_ray32(source_basis32(src, i), sc, w, i, px, out, i);
+    else shade_ray(source_basis(src, i, sc.M, sc.r_sky), sc, w, i, px, out, i);
 }
 
 // Batch shading: each pixel goes to its request's image.  A block shades
@@ -769,8 +852,9 @@ __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
             const int r = one ? rc : find_req(s_off, b.nreq, g);
             const ReqDev& q = one ? s_q : b.req[r];
             const int64_t i = g - s_off[r];
-            const Basis B = camera_basis(q.cam, i, q.sc.M, q.sc.r_sky);
-            shade_ray<F32>(B, q.sc, w, g, reinterpret_cast<float4*>(q.rgba) + i, Out{}, 0);
+            float4* px = reinterpret_cast<float4*>(q.rgba) + i;
+            if (F32) shade_ray32(camera_basis32(q.cam, i), q.sc, w, g, px, Out{}, 0);
+            else shade_ray(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, w, g, px, Out{}, 0);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
