@@ -107,8 +107,8 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
     if (n > ws.cap || ws.base == nullptr) {
         int64_t cap = n > 4096 ? n : 4096;
         // per ray: u0 (8 B), rec, res, q64rec (16 B each), clst, q64 (4 B each), path (1 B);
-        // the surrogate list (qsurrec 16 B, qsur 4 B) has kSlices * sur_slice_cap entries
-        const int64_t scap = bh::kSlices * bh::sur_slice_cap(cap);
+        // the surrogate list (qsurrec 16 B, qsur 4 B) has kSurSlices * sur_slice_cap entries
+        const int64_t scap = bh::kSurSlices * bh::sur_slice_cap(cap);
         const size_t sz16 = align256((size_t)cap * 16), sz8 = align256((size_t)cap * 8),
                      sz4 = align256((size_t)cap * 4), sz1 = align256((size_t)cap);
         const size_t szs16 = align256((size_t)scap * 16), szs4 = align256((size_t)scap * 4);

@@ -90,7 +90,7 @@ struct Work {
     double* u0;               // 1/|origin| per ray (explicit-ray mode only)
     double2* rec;             // start record {w0, phi1}; w0 = NaN: not in the main queue
     double2* res;             // result record {phi_end, r_hit}
-    int32_t* qsur;            // surrogate list (kSlices slices): ray indices ...
+    int32_t* qsur;            // surrogate list (kSurSlices slices): ray indices ...
     double2* qsurrec;         // ... and {b, w0}
     int32_t* rq;              // batch: request index of each ray
     int32_t* clst;            // class | (step evaluations << 3)
@@ -107,16 +107,18 @@ constexpr int kSlices = 8;                              // main-queue slices
 constexpr int kCtrBandSize = 0;                         // FP64 band queue length
 constexpr int kCtrBand = kCtrStride;                    // band queue head
 constexpr int kCtrMain = 2 * kCtrStride;                // kSlices main-queue heads
-constexpr int kCtrSur = kCtrMain + kSlices * kCtrStride; // kSlices surrogate-list lengths
-constexpr int kCtrInts = kCtrSur + kSlices * kCtrStride;
+constexpr int kSurSlices = 64;                          // surrogate-list slices
+constexpr int kCtrSur = kCtrMain + kSlices * kCtrStride; // kSurSlices surrogate-list lengths
+constexpr int kCtrInts = kCtrSur + kSurSlices * kCtrStride;
 
-// The surrogate list is filled at set-up in kSlices slices, one per residue
-// of the set-up block index mod kSlices; a slice holds at most the rays of its
-// blocks.  Capacity of one slice for n rays (the list needs kSlices times
-// this, at most n + kSlices * kBlock entries).
+// The surrogate list is filled at set-up in kSurSlices slices, one per
+// residue of the set-up block index mod kSurSlices (one atomic per block on
+// its slice's counter); a slice holds at most the rays of its blocks.
+// Capacity of one slice for n rays (the list needs kSurSlices times this, at
+// most n + kSurSlices * kBlock entries).
 __host__ __device__ inline int64_t sur_slice_cap(int64_t n) {
     const int64_t blocks = (n + kBlock - 1) / kBlock;
-    return (blocks + kSlices - 1) / kSlices * kBlock;
+    return (blocks + kSurSlices - 1) / kSurSlices * kBlock;
 }
 
 // Optional caller-owned outputs (mirrors bh_ray_out).

@@ -246,23 +246,33 @@ __device__ __forceinline__ void append_band(bool to_q64, int64_t i, double w0, d
     }
 }
 
-// Wave-aggregated append to slice (block index mod kSlices) of the surrogate
-// list: one atomic per wavefront that holds surrogate rays, spread over
-// kSlices counters.
+// Block-aggregated append to slice (block index mod kSurSlices) of the
+// surrogate list: one atomic per block that holds surrogate rays.  Every
+// thread of the block calls it (two barriers).
 __device__ __forceinline__ void append_sur(bool to_sur, int64_t i, double b, double w0,
                                            int64_t n, const Work& w) {
+    __shared__ int s_cnt[kBlock / 64];
+    __shared__ int s_base;
+    const int wv = threadIdx.x >> 6;
     const uint64_t m = __ballot(to_sur);
-    if (m) {
-        const int slice = (int)(blockIdx.x % (unsigned)kSlices);
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        int base = 0;
-        if (lane_id() == leader) base = atomicAdd(&w.ctr[kCtrSur + slice * kCtrStride], __popcll(m));
-        base = __shfl(base, leader);
-        if (to_sur) {
-            const int64_t slot = slice * sur_slice_cap(n) + base + rank_in(m);
-            w.qsur[slot] = (int32_t)i;
-            w.qsurrec[slot] = make_double2(b, w0);
+    if (lane_id() == 0) s_cnt[wv] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < kBlock / 64; ++k) {
+            const int c = s_cnt[k];
+            s_cnt[k] = tot;  // exclusive prefix over the block's wavefronts
+            tot += c;
         }
+        const int slice = (int)(blockIdx.x % (unsigned)kSurSlices);
+        s_base = tot > 0 ? atomicAdd(&w.ctr[kCtrSur + slice * kCtrStride], tot) : 0;
+    }
+    __syncthreads();
+    if (to_sur) {
+        const int slice = (int)(blockIdx.x % (unsigned)kSurSlices);
+        const int64_t slot = slice * sur_slice_cap(n) + s_base + s_cnt[wv] + rank_in(m);
+        w.qsur[slot] = (int32_t)i;
+        w.qsurrec[slot] = make_double2(b, w0);
     }
 }
 
@@ -895,7 +905,7 @@ __global__ __launch_bounds__(kBlock) void k_count_paths(int64_t n, const uint8_t
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 hipError_t launch_reset(int32_t* ctr, hipStream_t s) {
-    k_reset<<<1, 64, 0, s>>>(ctr);
+    k_reset<<<1, 256, 0, s>>>(ctr);
     return hipGetLastError();
 }
 
@@ -976,7 +986,7 @@ hipError_t launch_batch_begin(const BatchDev& b, hipStream_t s) {
 // the group's first ray) and w its rays.
 hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int precision,
                         int cus, int grid_blocks, int chunk, hipStream_t s) {
-    k_reset<<<1, 64, 0, s>>>(w.ctr);
+    k_reset<<<1, 256, 0, s>>>(w.ctr);
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
     if (b.total > 0) k_setup_batch<<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
     hipError_t e = hipGetLastError();

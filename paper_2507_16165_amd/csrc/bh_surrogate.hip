@@ -552,39 +552,44 @@ __device__ inline void sur_finish(const SurRender& a, int id, double w0, float b
     a.w.clst[id] = 0;  // SKY, no integration steps
 }
 
-// Entry of listed ray j of tile t (tile numbering runs over the slices in
-// order); lanes past the end of their slice read the slice's first entry.
+// Entry of listed ray j of tile t: tiles are numbered over the slices in
+// order; first[s] is the first tile of slice s (first[kSurSlices] = all
+// tiles), cnt[s] its length.  Lanes past the end of their slice read the
+// slice's first entry.
 struct SurEntry {
     int64_t slot;
     bool valid;
 };
 
-__device__ inline SurEntry sur_entry(const int* cnt, int64_t slice_cap, int64_t t, int lane) {
-    int s = 0;
-    int64_t first = 0;  // first tile of slice s
-#pragma unroll
-    for (int q = 0; q < kSlices - 1; ++q) {
-        const int64_t nt = (cnt[s] + 31) / 32;
-        if (t >= first + nt) {
-            first += nt;
-            ++s;
-        }
+__device__ inline SurEntry sur_entry(const int* cnt, const int* first, int64_t slice_cap,
+                                     int64_t t, int lane) {
+    int lo = 0, hi = kSurSlices - 1;  // last slice with first[s] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= t) lo = mid;
+        else hi = mid - 1;
     }
-    const int64_t j = (t - first) * 32 + lane;
-    const bool valid = j < cnt[s];
-    return {s * slice_cap + (valid ? j : 0), valid};
+    const int64_t j = (t - first[lo]) * 32 + lane;
+    const bool valid = j < cnt[lo];
+    return {lo * slice_cap + (valid ? j : 0), valid};
 }
 
 __global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void k_sur_render(const void* __restrict__ pack, SurRender a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    int cnt[kSlices];
-    int64_t tiles = 0;
-#pragma unroll
-    for (int q = 0; q < kSlices; ++q) {
-        cnt[q] = a.w.ctr[kCtrSur + q * kCtrStride];
-        tiles += (cnt[q] + 31) / 32;
+    __shared__ int s_cnt[kSurSlices], s_first[kSurSlices + 1];
+    if (threadIdx.x < kSurSlices) s_cnt[threadIdx.x] = a.w.ctr[kCtrSur + threadIdx.x * kCtrStride];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int q = 0; q < kSurSlices; ++q) {
+            s_first[q] = t;
+            t += (s_cnt[q] + 31) / 32;
+        }
+        s_first[kSurSlices] = t;
     }
+    __syncthreads();
+    const int64_t tiles = s_first[kSurSlices];
     constexpr int wpb = kInferThreads / 64;
     if ((int64_t)blockIdx.x * wpb >= tiles) return;  // block-uniform: nothing for this block
     load_pack(pack, smem);
@@ -598,7 +603,7 @@ void k_sur_render(const void* __restrict__ pack, SurRender a) {
     int id = 0;
     double2 rec = make_double2(10.0, 0.0);
     if (t < tiles) {
-        e = sur_entry(cnt, a.slice_cap, t, l & 31);
+        e = sur_entry(s_cnt, s_first, a.slice_cap, t, l & 31);
         id = a.w.qsur[e.slot];
         rec = a.w.qsurrec[e.slot];
     }
@@ -608,7 +613,7 @@ void k_sur_render(const void* __restrict__ pack, SurRender a) {
         int idn = 0;
         double2 recn = make_double2(10.0, 0.0);
         if (t + nw < tiles) {
-            en = sur_entry(cnt, a.slice_cap, t + nw, l & 31);
+            en = sur_entry(s_cnt, s_first, a.slice_cap, t + nw, l & 31);
             idn = a.w.qsur[en.slot];
             recn = a.w.qsurrec[en.slot];
         }
