@@ -105,6 +105,9 @@ typedef struct {
                                 effective potential peaks at b = 3 sqrt(3) M)          */
     int    grid_blocks;      /* persistent integrator grid, 256-thread blocks; 0 = auto */
     int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto  */
+    int    samples_side;     /* bh_render: n x n rays per pixel at the stratified
+                                sub-pixel centres, averaged (box filter); 0 or 1 =
+                                one ray through the pixel centre; at most 16        */
     int    batch_groups;     /* batches: consecutive request groups traced one after
                                 another (1 = one launch sequence for all); 0 = auto:
                                 about 64M rays per group                             */
@@ -143,8 +146,12 @@ bh_status bh_trace_rays(const double* origin, const double* dir, int64_t n,
  * row 0 at the top): checker sky (1,1,1,1)/(0.1,0.1,0.1,1), disk
  * (1, 0.6, 0.2) * I with alpha 1, black (0,0,0,1) for captured, unresolved
  * and invalid rays.  per_pixel (may be NULL) receives per-ray records indexed
- * y*width + x.  Paper: Introduction (one ray per pixel), Results (renders
- * with an Einstein ring). */
+ * y*width + x.  With opt->samples_side = n > 1 each pixel is the mean of
+ * n*n rays through the centres of an n x n grid of sub-pixels (the rays of a
+ * (n*width) x (n*height) image of the same camera), and per_pixel then holds
+ * n*n*width*height records indexed (n*y + j)*(n*width) + (n*x + i).
+ * Paper: Introduction (one ray per pixel; more samples per pixel are the
+ * Results' image-quality axis), Results (renders with an Einstein ring). */
 bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
                     float* rgba, const bh_ray_out* per_pixel, void* stream);
 

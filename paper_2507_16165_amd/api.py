@@ -41,7 +41,7 @@ class Options(C.Structure):
                 ("h0_fp32", C.c_double),
                 ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
                 ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
-                ("batch_groups", C.c_int),
+                ("samples_side", C.c_int), ("batch_groups", C.c_int),
                 ("surrogate", C.c_void_p)]
 
 
@@ -200,11 +200,12 @@ def render(camera: inputs.Camera, scene: inputs.Scene, opt: Options | None = Non
         rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
     assert rgba.dtype == torch.float32 and rgba.is_contiguous() and rgba.numel() == H * W * 4
     out, ro = (None, None)
+    opt = opt or options()
+    n = max(1, int(opt.samples_side))
     if fields:
-        out, ro = _alloc_out(H * W, fields, rgba.device)
+        out, ro = _alloc_out(H * W * n * n, fields, rgba.device)  # one record per sample
     cam = camera_struct(camera)
     sc = scene_struct(scene)
-    opt = opt or options()
     check(lib().bh_render(C.byref(cam), C.byref(sc), C.byref(opt), rgba.data_ptr(),
                           C.byref(ro) if ro is not None else None, _stream(stream)))
     return rgba, out

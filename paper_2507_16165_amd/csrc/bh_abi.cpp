@@ -176,6 +176,8 @@ bh_status check_opt(const bh_options* o) {
         !finite_pos(o->max_phi))
         return fail(BH_ERR_ARG, "h0, h0_fp32, hmax and max_phi must be > 0");
     if (o->max_steps < 1) return fail(BH_ERR_ARG, "max_steps must be >= 1");
+    if (o->samples_side < 0 || o->samples_side > 16)
+        return fail(BH_ERR_ARG, "samples_side must be in [0, 16]");
     if (o->grid_blocks < 0 || o->chunk < 0 || o->batch_groups < 0)
         return fail(BH_ERR_ARG, "launch shape and batch groups must be >= 0");
     if (o->chunk % 64 != 0) return fail(BH_ERR_ARG, "chunk must be a multiple of 64");
@@ -288,7 +290,8 @@ bh::DevCam make_cam(const bh_camera* cam) {
 
 // The shared sequence: reset counters, set-up, integrate, shade.
 bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const bh_scene* scene,
-              const bh_options* opt, float* rgba, const bh_ray_out* out, hipStream_t stream) {
+              const bh_options* opt, float* rgba, const bh_ray_out* out, hipStream_t stream,
+              int samples_side = 1) {
     Workspace* ws = nullptr;
     bh_status st = get_workspace(src.n, stream, &ws);
     if (st != BH_OK) return st;
@@ -325,7 +328,10 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "integrate");
     t = timing_begin(2, stream);
-    e = bh::launch_shade(src, sc, w, rgba, dev_out(out), opt->precision, stream);
+    e = samples_side > 1
+            ? bh::launch_shade_samples(src, sc, w, rgba, dev_out(out), opt->precision, samples_side,
+                                       stream)
+            : bh::launch_shade(src, sc, w, rgba, dev_out(out), opt->precision, stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "shade");
     ws->last_n = src.n;
@@ -381,10 +387,18 @@ bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_option
     if ((st = check_opt(opt)) != BH_OK) return st;
     if ((st = check_camera(cam, scene)) != BH_OK) return st;
     if (!rgba) return fail(BH_ERR_ARG, "rgba is NULL");
+    const int n = opt->samples_side > 1 ? opt->samples_side : 1;
+    // n x n samples per pixel: the rays of the same camera at n times the
+    // resolution (their pixel centres are the stratified sub-pixel centres)
+    bh_camera sub = *cam;
+    if ((int64_t)cam->width * n * cam->height * n > INT32_MAX)
+        return fail(BH_ERR_ARG, "image * samples must have < 2^31 rays");
+    sub.width = cam->width * n;
+    sub.height = cam->height * n;
     bh::Source src{};
-    src.n = (int64_t)cam->width * cam->height;
-    src.cam = make_cam(cam);
-    return run(src, false, 1.0 / cam->r, scene, opt, rgba, per_pixel, (hipStream_t)stream);
+    src.n = (int64_t)sub.width * sub.height;
+    src.cam = make_cam(&sub);
+    return run(src, false, 1.0 / cam->r, scene, opt, rgba, per_pixel, (hipStream_t)stream, n);
 }
 
 bh_status bh_reserve(int64_t n) {
@@ -473,6 +487,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     bh_status st = check_opt(opt);
     if (st != BH_OK) return st;
     if (opt->surrogate) return fail(BH_ERR_UNSUPPORTED, "batches do not route to the surrogate");
+    if (opt->samples_side > 1) return fail(BH_ERR_UNSUPPORTED, "batches trace one ray per pixel");
     std::vector<bh::ReqDev> req(n);
     std::vector<bh::BatchConst> bc(n);
     std::vector<int64_t> off(n + 1, 0);

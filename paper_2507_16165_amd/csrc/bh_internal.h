@@ -177,6 +177,8 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
                             int grid_blocks, int chunk, hipStream_t s);
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
                         const Out& out, int precision, hipStream_t s);
+hipError_t launch_shade_samples(const Source& src, const DevScene& sc, const Work& w, float* rgba,
+                                const Out& out, int precision, int n, hipStream_t s);
 // Surrogate (bh_surrogate.hip): the device trust map (NULL until built) and
 // inference pack of a handle, and the render-path kernel over PATH_SUR rays.
 const uint8_t* surrogate_trust(const bh_surrogate* s);

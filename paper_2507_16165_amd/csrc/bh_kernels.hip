@@ -879,6 +879,35 @@ __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
     }
 }
 
+// n x n samples per pixel: src is the (n W) x (n H) sample camera; thread
+// (x, y) shades its pixel's n*n samples in a fixed order and writes their mean
+// to the W x H image (per-ray records go to the sample index).
+template <bool F32>
+__global__ __launch_bounds__(kBlock) void k_shade_samples(Source src, DevScene sc, Work w,
+                                                          float* rgba, Out out, int n) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int Wn = src.cam.W, W = Wn / n;
+    const int64_t npx = src.n / ((int64_t)n * n);
+    if (p >= npx) return;
+    const int64_t y = p / W, x = p - y * W;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) {
+            const int64_t q = (y * n + j) * Wn + (x * n + i);
+            float4 c;
+            if (F32) shade_ray32(source_basis32(src, q), sc, w, q, &c, out, q);
+            else shade_ray(source_basis(src, q, sc.M, sc.r_sky), sc, w, q, &c, out, q);
+            acc.x += c.x;
+            acc.y += c.y;
+            acc.z += c.z;
+            acc.w += c.w;
+        }
+    }
+    const float inv = 1.0f / (float)(n * n);
+    reinterpret_cast<float4*>(rgba)[p] = make_float4(acc.x * inv, acc.y * inv, acc.z * inv,
+                                                     acc.w * inv);
+}
+
 // Batch start time and completion counters.
 __global__ void k_batch_begin(BatchDev b) {
     for (int r = threadIdx.x; r < b.nreq; r += blockDim.x) b.done[r] = 0;
@@ -1028,6 +1057,15 @@ hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, fl
     if (src.n == 0) return hipSuccess;
     if (precision == 1) k_shade<true><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
     else k_shade<false><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade_samples(const Source& src, const DevScene& sc, const Work& w, float* rgba,
+                                const Out& out, int precision, int n, hipStream_t s) {
+    const int64_t npx = src.n / ((int64_t)n * n);
+    if (npx == 0) return hipSuccess;
+    if (precision == 1) k_shade_samples<true><<<blocks_for(npx), kBlock, 0, s>>>(src, sc, w, rgba, out, n);
+    else k_shade_samples<false><<<blocks_for(npx), kBlock, 0, s>>>(src, sc, w, rgba, out, n);
     return hipGetLastError();
 }
 

@@ -68,6 +68,10 @@ def test_render_rejects_null_and_bad_options():
     assert _render(cam, sc, api.options(rtol=-1.0)) == api.BH_ERR_ARG
     assert _render(cam, sc, api.options(chunk=100)) == api.BH_ERR_ARG
     assert _render(cam, sc, api.options(max_steps=0)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(h0_fp32=0.0)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(samples_side=17)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(samples_side=-1)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(batch_groups=-1)) == api.BH_ERR_ARG
     L = api.lib()
     assert L.bh_render(None, None, None, None, None, None) == api.BH_ERR_ARG
     assert L.bh_default_options(None) == api.BH_ERR_ARG
@@ -119,5 +123,7 @@ def test_batch_argument_checks():
     reqs[0] = api.Request(api.camera_struct(inputs.Camera(30.0, 90, 0, 60, 8, 8)),
                           api.scene_struct(inputs.Scene(M=1.0)), None)
     assert L.bh_batch_create(reqs, 1, C.byref(o), 0, C.byref(h)) == api.BH_ERR_ARG
+    o2 = api.options(samples_side=2)
+    assert L.bh_batch_create(reqs, 1, C.byref(o2), 0, C.byref(h)) == api.BH_ERR_UNSUPPORTED
     assert L.bh_batch_launch(None, None) == api.BH_ERR_ARG
     assert L.bh_batch_destroy(None) == api.BH_OK

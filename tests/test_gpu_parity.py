@@ -221,3 +221,36 @@ def test_counts(bh):
     assert sum(c.values()) == 4096
     assert 250 < c["setup"] <= 300  # analytic captures (below the band)
     assert c["fp64"] > 0 and c["fp32"] > 3000
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_samples_per_pixel(bh, ref, precision):
+    """n x n samples per pixel: the per-sample records equal the oracle's
+    render of the same camera at n times the resolution, and each pixel is
+    the mean of its n*n samples' colours (pixels whose samples are all clear
+    of the ambiguity zones)."""
+    from parity import TOL, near_cell_boundary
+    n = 3
+    f = inputs.Frame(inputs.Camera(25.0, 70.0, 40.0, 60.0, 40, 24), inputs.scene_in_m(1.0, (6.0, 20.0)))
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    rgba, out = gpu_render(bh, f, p, samples_side=n)
+    W, H = f.camera.width, f.camera.height
+    sub = inputs.Camera(f.camera.r, f.camera.incl_deg, f.camera.azim_deg, f.camera.fov_deg, W * n, H * n)
+    r_rgba, r_rays = ref.render(ref_camera(ref, sub), ref_scene(ref, f.scene))
+    compare(r_rays, out, f.scene, precision)
+    t = TOL[precision]
+    rc, gc = r_rays.cls.astype(int), out["cls"].astype(int)
+    ok = (rc == gc) & ~(np.abs(r_rays.b - B_CRIT) < 0.05)
+    ok &= ~(near_cell_boundary(r_rays.exit_dir, f.scene.checker_deg, t["tau_theta"]) & (rc == 0))
+    blocks = lambda a: a.reshape(H, n, W, n, *a.shape[2:]).swapaxes(1, 2)  # (H, W, n, n, ...)
+    ok_px = blocks(ok.reshape(H * n, W * n)).all(axis=(2, 3))
+    want = blocks(r_rgba.astype(np.float64)).mean(axis=(2, 3))
+    tol = blocks(np.where((rc == 2)[:, None], 4.0 * t["r_rel"] * np.abs(r_rgba.reshape(-1, 4)) + 1e-7,
+                          t["rgba"]).reshape(H * n, W * n, 4)).mean(axis=(2, 3))
+    d = np.abs(rgba.astype(np.float64) - want)
+    assert ok_px.sum() > 0.8 * W * H
+    assert np.all((d <= tol + 1e-6)[ok_px]), d[ok_px].max()
+    # one sample per pixel is the plain render
+    rgba1, _ = gpu_render(bh, f, p, samples_side=1)
+    rgba0, _ = gpu_render(bh, f, p)
+    np.testing.assert_array_equal(rgba1, rgba0)
