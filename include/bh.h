@@ -76,6 +76,13 @@ typedef struct {
     double disk_rout;
     double disk_power;   /* -3 for the r^-3 emissivity                          */
     double checker_deg;  /* checker cell in degrees of theta and varphi (> 0)  */
+    const float* sky_tex;/* optional equirectangular sky image instead of the
+                            checker: device, tex_h rows (theta 0 .. pi) of tex_w
+                            RGBA float texels (varphi 0 .. 2 pi), texel centres at
+                            ((i + 1/2) 2 pi / tex_w, (j + 1/2) pi / tex_h);
+                            bilinear filtering, wrapping in varphi and clamped at
+                            the poles; caller-owned; NULL: the checker          */
+    int    tex_w, tex_h; /* >= 1 each, tex_w * tex_h <= 2^28 when sky_tex is set */
 } bh_scene;
 
 /* Pinhole camera looking at the hole: position r (sin i cos a, sin i sin a,

@@ -363,6 +363,7 @@ static int scene_ok(const bhr_scene* sc)
     if (!sc) return 0;
     if (!(sc->M >= 0.0) || !(sc->r_sky > 0.0) || !(sc->checker_deg > 0.0)) return 0;
     if (sc->has_disk && !(sc->disk_rin > 0.0 && sc->disk_rin < sc->disk_rout)) return 0;
+    if (sc->sky_tex && !(sc->tex_w >= 1 && sc->tex_h >= 1)) return 0;
     return 1;
 }
 
@@ -380,13 +381,46 @@ int bhr_trace_rays(const double* origin, const double* dir, int64_t n,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Shading: procedural checker sky, disk emissivity, black otherwise.        */
+/* Shading: sky (procedural checker or an equirectangular image), disk       */
+/* emissivity, black otherwise.                                              */
 /* ------------------------------------------------------------------------ */
+void bhr_sky_sample(const bhr_scene* sc, double theta, double varphi, double rgba[4])
+{
+    const int W = sc->tex_w, H = sc->tex_h;
+    /* continuous texel coordinates: centres at integers */
+    const double u = varphi / (2.0 * PI) * W - 0.5;
+    const double v = theta / PI * H - 0.5;
+    const double i0f = floor(u), j0f = floor(v);
+    const double fu = u - i0f, fv = v - j0f;
+    long i0 = (long)i0f % W;
+    if (i0 < 0) i0 += W;
+    const long i1 = (i0 + 1) % W;
+    long j0 = (long)j0f, j1 = j0 + 1;
+    if (j0 < 0) j0 = 0;
+    if (j0 > H - 1) j0 = H - 1;
+    if (j1 < 0) j1 = 0;
+    if (j1 > H - 1) j1 = H - 1;
+    for (int c = 0; c < 4; ++c) {
+        const double t00 = sc->sky_tex[((size_t)j0 * W + i0) * 4 + c];
+        const double t10 = sc->sky_tex[((size_t)j0 * W + i1) * 4 + c];
+        const double t01 = sc->sky_tex[((size_t)j1 * W + i0) * 4 + c];
+        const double t11 = sc->sky_tex[((size_t)j1 * W + i1) * 4 + c];
+        rgba[c] = (1.0 - fv) * ((1.0 - fu) * t00 + fu * t10) + fv * ((1.0 - fu) * t01 + fu * t11);
+    }
+}
+
 void bhr_shade(const bhr_scene* sc, int cls, const double s[3], double r_hit, float rgba[4])
 {
     rgba[0] = rgba[1] = rgba[2] = 0.0f;
     rgba[3] = 1.0f;
-    if (cls == BHR_SKY) {
+    if (cls == BHR_SKY && sc->sky_tex) {
+        const double theta = atan2(hypot(s[0], s[1]), s[2]);
+        double varphi = atan2(s[1], s[0]);
+        if (varphi < 0.0) varphi += 2.0 * PI;
+        double t[4];
+        bhr_sky_sample(sc, theta, varphi, t);
+        for (int c = 0; c < 4; ++c) rgba[c] = (float)t[c];
+    } else if (cls == BHR_SKY) {
         const double theta = atan2(hypot(s[0], s[1]), s[2]);
         double varphi = atan2(s[1], s[0]);
         if (varphi < 0.0) varphi += 2.0 * PI;

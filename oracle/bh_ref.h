@@ -60,6 +60,10 @@ typedef struct {
     double disk_rout;    /* outer disk radius                                 */
     double disk_power;   /* emissivity I = (r / r_in)^power (power = -3)      */
     double checker_deg;  /* checker cell size on the sky sphere, degrees      */
+    const float* sky_tex;/* optional equirectangular sky image (host, RGBA floats,
+                            tex_h rows from theta = 0 to pi, tex_w columns from
+                            varphi = 0 to 2 pi); NULL: the checker             */
+    int    tex_w, tex_h;
 } bhr_scene;
 
 typedef struct {
@@ -113,6 +117,11 @@ int bhr_render_rows(const bhr_camera* cam, const bhr_scene* sc, const bhr_option
 
 /* Colour of one ray from its class, end vector and hit radius. */
 void bhr_shade(const bhr_scene* sc, int cls, const double exit_dir[3], double r_hit, float rgba[4]);
+/* Bilinear sample of the sky image at direction angles (theta, varphi):
+ * texel (i, j) covers column i, row j with its centre at
+ * varphi = 2 pi (i + 1/2) / tex_w, theta = pi (j + 1/2) / tex_h; columns wrap
+ * around in varphi, rows are clamped at the poles.  Computed in FP64. */
+void bhr_sky_sample(const bhr_scene* sc, double theta, double varphi, double rgba[4]);
 
 /* One Dormand-Prince 5(4) step of the photon-orbit system from (u, w) with
  * step h: y_out = 5th-order solution, err = 5th minus embedded 4th order. */

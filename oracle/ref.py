@@ -37,7 +37,8 @@ def build(verbose: bool = False) -> str:
 class Scene(C.Structure):
     _fields_ = [("M", C.c_double), ("r_sky", C.c_double), ("has_disk", C.c_int),
                 ("disk_rin", C.c_double), ("disk_rout", C.c_double),
-                ("disk_power", C.c_double), ("checker_deg", C.c_double)]
+                ("disk_power", C.c_double), ("checker_deg", C.c_double),
+                ("sky_tex", C.c_void_p), ("tex_w", C.c_int), ("tex_h", C.c_int)]
 
 
 class Camera(C.Structure):
@@ -75,6 +76,8 @@ def lib():
         L.bhr_render_rows.argtypes = [C.POINTER(Camera), C.POINTER(Scene), C.POINTER(Options),
                                       C.c_int, C.c_int, C.c_void_p, C.POINTER(Out)]
         L.bhr_shade.argtypes = [C.POINTER(Scene), C.c_int, C.c_void_p, C.c_double, C.c_void_p]
+        L.bhr_sky_sample.argtypes = [C.POINTER(Scene), C.c_double, C.c_double, C.c_void_p]
+        L.bhr_sky_sample.restype = None
         L.bhr_shade.restype = None
         L.bhr_dopri5_step.argtypes = [C.c_double, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
         L.bhr_dopri5_step.restype = None
@@ -84,12 +87,26 @@ def lib():
     return _lib
 
 
-def scene(M=1.0, r_sky=None, disk=None, disk_power=-3.0, checker_deg=10.0) -> Scene:
-    """``r_sky`` defaults to 1000 M; ``disk`` is ``(r_in, r_out)`` or None."""
+def scene(M=1.0, r_sky=None, disk=None, disk_power=-3.0, checker_deg=10.0, sky_tex=None) -> Scene:
+    """``r_sky`` defaults to 1000 M; ``disk`` is ``(r_in, r_out)`` or None;
+    ``sky_tex`` an optional (tex_h, tex_w, 4) float32 equirectangular image
+    (kept alive on the returned struct)."""
     if r_sky is None:
         r_sky = 1000.0 * M if M > 0 else 1000.0
     rin, rout = disk if disk is not None else (0.0, 0.0)
-    return Scene(M, r_sky, 1 if disk is not None else 0, rin, rout, disk_power, checker_deg)
+    s = Scene(M, r_sky, 1 if disk is not None else 0, rin, rout, disk_power, checker_deg, None, 0, 0)
+    if sky_tex is not None:
+        t = np.ascontiguousarray(sky_tex, dtype=np.float32)
+        assert t.ndim == 3 and t.shape[2] == 4
+        s.sky_tex, s.tex_h, s.tex_w = t.ctypes.data, t.shape[0], t.shape[1]
+        s._tex = t
+    return s
+
+
+def sky_sample(sc: Scene, theta: float, varphi: float) -> np.ndarray:
+    out = np.zeros(4)
+    lib().bhr_sky_sample(C.byref(sc), C.c_double(theta), C.c_double(varphi), out.ctypes.data)
+    return out
 
 
 def camera(r, incl_deg, azim_deg, fov_deg, width, height) -> Camera:

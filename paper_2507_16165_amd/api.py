@@ -27,7 +27,8 @@ class BhError(RuntimeError):
 class Scene(C.Structure):
     _fields_ = [("M", C.c_double), ("r_sky", C.c_double), ("has_disk", C.c_int),
                 ("disk_rin", C.c_double), ("disk_rout", C.c_double),
-                ("disk_power", C.c_double), ("checker_deg", C.c_double)]
+                ("disk_power", C.c_double), ("checker_deg", C.c_double),
+                ("sky_tex", C.c_void_p), ("tex_w", C.c_int), ("tex_h", C.c_int)]
 
 
 class Camera(C.Structure):
@@ -141,10 +142,32 @@ def options(**overrides) -> Options:
     return o
 
 
+_tex_cache = {}  # id(host image) -> (host image, device copy): the device copy lives as long
+
+
+def sky_texture_device(tex):
+    """Device copy (cached) of a (tex_h, tex_w, 4) float32 sky image; a torch
+    CUDA tensor is used as it is."""
+    import numpy as np
+    import torch
+    if isinstance(tex, torch.Tensor):
+        assert tex.is_cuda and tex.dtype == torch.float32 and tex.is_contiguous()
+        return tex
+    hit = _tex_cache.get(id(tex))
+    if hit is None or hit[0] is not tex:
+        hit = (tex, torch.from_numpy(np.ascontiguousarray(tex, dtype=np.float32)).cuda())
+        _tex_cache[id(tex)] = hit
+    return hit[1]
+
+
 def scene_struct(s: inputs.Scene) -> Scene:
     rin, rout = s.disk if s.disk is not None else (0.0, 0.0)
-    return Scene(s.M, s.r_sky, 1 if s.disk is not None else 0, rin, rout, s.disk_power,
-                 s.checker_deg)
+    sc = Scene(s.M, s.r_sky, 1 if s.disk is not None else 0, rin, rout, s.disk_power,
+               s.checker_deg, None, 0, 0)
+    if s.sky_tex is not None:
+        t = sky_texture_device(s.sky_tex)
+        sc.sky_tex, sc.tex_h, sc.tex_w = t.data_ptr(), t.shape[0], t.shape[1]
+    return sc
 
 
 def camera_struct(c: inputs.Camera) -> Camera:

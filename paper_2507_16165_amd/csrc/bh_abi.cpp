@@ -160,6 +160,12 @@ bh_status check_scene(const bh_scene* sc) {
             return fail(BH_ERR_ARG, "disk needs 0 < r_in < r_out");
         if (!isfinite(sc->disk_power)) return fail(BH_ERR_ARG, "disk_power must be finite");
     }
+    if (sc->sky_tex) {
+        if (sc->tex_w < 1 || sc->tex_h < 1 || (int64_t)sc->tex_w * sc->tex_h > (1ll << 28))
+            return fail(BH_ERR_ARG, "sky texture needs 1 <= tex_w, tex_h and tex_w * tex_h <= 2^28");
+        if ((uintptr_t)sc->sky_tex % 16 != 0)
+            return fail(BH_ERR_ARG, "sky texture must be 16-byte aligned (RGBA float texels)");
+    }
     return BH_OK;
 }
 
@@ -197,6 +203,11 @@ bh::DevScene dev_scene(const bh_scene* sc) {
     d.urout = sc->has_disk ? 1.0 / sc->disk_rout : 0.0;
     d.cell_rad = sc->checker_deg * kPi / 180.0;
     d.inv_cell = 1.0 / d.cell_rad;
+    d.tex = reinterpret_cast<const float4*>(sc->sky_tex);
+    d.tex_w = sc->sky_tex ? sc->tex_w : 0;
+    d.tex_h = sc->sky_tex ? sc->tex_h : 0;
+    d.tex_su = sc->sky_tex ? sc->tex_w / (2.0 * kPi) : 0.0;
+    d.tex_sv = sc->sky_tex ? sc->tex_h / kPi : 0.0;
     return d;
 }
 

@@ -53,6 +53,9 @@ struct DevScene {
     double urin, urout;       // 1/rin, 1/rout: the disk test runs on u = 1/r
     double cell_rad;          // checker cell in radians
     double inv_cell;          // 1 / cell_rad
+    const float4* tex;        // sky image (NULL: checker), tex_h rows of tex_w texels
+    double tex_su, tex_sv;    // texels per radian: tex_w / (2 pi), tex_h / pi
+    int tex_w, tex_h;
     int has_disk;
 };
 

@@ -741,6 +741,49 @@ __device__ __forceinline__ Basis32 source_basis32(const Source& src, int64_t i) 
     return camera_basis32(src.cam, i);
 }
 
+// Bilinear sample of the sky image at (theta, varphi): texel centres at
+// integer continuous coordinates u = varphi tex_w / (2 pi) - 1/2,
+// v = theta tex_h / pi - 1/2; columns wrap, rows clamp.  FP32 and FP64 forms.
+__device__ __forceinline__ float4 sky_texel32(const DevScene& sc, float theta, float varphi) {
+    const int W = sc.tex_w, H = sc.tex_h;
+    const float u = fmaf(varphi, (float)sc.tex_su, -0.5f);
+    const float v = fmaf(theta, (float)sc.tex_sv, -0.5f);
+    const float uf = floorf(u), vf = floorf(v);
+    const float fu = u - uf, fv = v - vf;
+    int i0 = (int)uf % W;
+    if (i0 < 0) i0 += W;
+    const int i1 = i0 + 1 == W ? 0 : i0 + 1;
+    const int j0 = min(max((int)vf, 0), H - 1), j1 = min(max((int)vf + 1, 0), H - 1);
+    const float4 a = sc.tex[(int64_t)j0 * W + i0], b = sc.tex[(int64_t)j0 * W + i1];
+    const float4 c = sc.tex[(int64_t)j1 * W + i0], d = sc.tex[(int64_t)j1 * W + i1];
+    auto lerp2 = [fu, fv](float p, float q, float r, float t) {
+        return fmaf(fv, fmaf(fu, t - r, r) - fmaf(fu, q - p, p), fmaf(fu, q - p, p));
+    };
+    return make_float4(lerp2(a.x, b.x, c.x, d.x), lerp2(a.y, b.y, c.y, d.y),
+                       lerp2(a.z, b.z, c.z, d.z), lerp2(a.w, b.w, c.w, d.w));
+}
+
+__device__ __forceinline__ float4 sky_texel64(const DevScene& sc, double theta, double varphi) {
+    const int W = sc.tex_w, H = sc.tex_h;
+    const double u = fma(varphi, sc.tex_su, -0.5);
+    const double v = fma(theta, sc.tex_sv, -0.5);
+    const double uf = floor(u), vf = floor(v);
+    const double fu = u - uf, fv = v - vf;
+    int64_t i0 = (int64_t)uf % W;
+    if (i0 < 0) i0 += W;
+    const int64_t i1 = i0 + 1 == W ? 0 : i0 + 1;
+    const int64_t j0 = min(max((int64_t)vf, (int64_t)0), (int64_t)H - 1);
+    const int64_t j1 = min(max((int64_t)vf + 1, (int64_t)0), (int64_t)H - 1);
+    const float4 a = sc.tex[j0 * W + i0], b = sc.tex[j0 * W + i1];
+    const float4 c = sc.tex[j1 * W + i0], d = sc.tex[j1 * W + i1];
+    auto lerp2 = [fu, fv](double p, double q, double r, double t) {
+        const double top = fma(fu, q - p, p), bot = fma(fu, t - r, r);
+        return (float)fma(fv, bot - top, top);
+    };
+    return make_float4(lerp2(a.x, b.x, c.x, d.x), lerp2(a.y, b.y, c.y, d.y),
+                       lerp2(a.z, b.z, c.z, d.z), lerp2(a.w, b.w, c.w, d.w));
+}
+
 __device__ __forceinline__ float4 shade_px32(const Basis32& B, const DevScene& sc, uint8_t cls,
                                              double phi, double r_hit, float sv[3]) {
     float sf, cf;
@@ -750,13 +793,17 @@ __device__ __forceinline__ float4 shade_px32(const Basis32& B, const DevScene& s
     if (cls == INVALID) sv[0] = sv[1] = sv[2] = 0.0f;
     float4 px = make_float4(0.f, 0.f, 0.f, 1.f);
     if (cls == SKY) {
-        const float icell = (float)sc.inv_cell;
         const float theta = atan2f(sqrtf(fmaf(sv[0], sv[0], sv[1] * sv[1])), sv[2]);
         float varphi = atan2f(sv[1], sv[0]);
         if (varphi < 0.0f) varphi += 6.28318531f;
-        const int parity = ((int)floorf(theta * icell) + (int)floorf(varphi * icell)) & 1;
-        const float g = parity ? 0.1f : 1.0f;
-        px = make_float4(g, g, g, 1.f);
+        if (sc.tex) {
+            px = sky_texel32(sc, theta, varphi);
+        } else {
+            const float icell = (float)sc.inv_cell;
+            const int parity = ((int)floorf(theta * icell) + (int)floorf(varphi * icell)) & 1;
+            const float g = parity ? 0.1f : 1.0f;
+            px = make_float4(g, g, g, 1.f);
+        }
     } else if (cls == DISK) {
         const float I = powf((float)(r_hit / sc.rin), (float)sc.power);
         px = make_float4(I, 0.6f * I, 0.2f * I, 1.f);
@@ -802,10 +849,14 @@ __device__ __forceinline__ void shade_ray(const Basis& B, const DevScene& sc, co
         const double theta = atan2(hypot(s[0], s[1]), s[2]);
         double varphi = atan2(s[1], s[0]);
         if (varphi < 0.0) varphi += 2.0 * kPi;
-        const long parity =
-            ((long)floor(theta * sc.inv_cell) + (long)floor(varphi * sc.inv_cell)) & 1L;
-        const float g = parity ? 0.1f : 1.0f;
-        px = make_float4(g, g, g, 1.f);
+        if (sc.tex) {
+            px = sky_texel64(sc, theta, varphi);
+        } else {
+            const long parity =
+                ((long)floor(theta * sc.inv_cell) + (long)floor(varphi * sc.inv_cell)) & 1L;
+            const float g = parity ? 0.1f : 1.0f;
+            px = make_float4(g, g, g, 1.f);
+        }
     } else if (cls == DISK) {
         const double I = pow(r_hit / sc.rin, sc.power);
         px = make_float4((float)I, (float)(0.6 * I), (float)(0.2 * I), 1.f);

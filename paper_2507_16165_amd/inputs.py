@@ -25,6 +25,7 @@ class Scene:
     disk: tuple | None = None          # (r_in, r_out), absolute units
     disk_power: float = DISK_POWER
     checker_deg: float = CHECKER_DEG
+    sky_tex: object = field(default=None, compare=False)  # (h, w, 4) float32 sky image, or None
 
 
 @dataclass(frozen=True)
@@ -108,6 +109,41 @@ def serving_batch(n: int = 512, seed: int = 5, sizes=BATCH_SIZES) -> list[Frame]
 def shrink(frame: Frame, width: int, height: int) -> Frame:
     """Same camera and scene at another resolution (for oracle-sized checks)."""
     return replace(frame, camera=replace(frame.camera, width=width, height=height))
+
+
+# -- sky images -----------------------------------------------------------------
+
+def sky_texture(width: int = 1024, height: int = 512, seed: int = 7, terms: int = 12,
+                stars: int = 400) -> np.ndarray:
+    """A seeded procedural equirectangular sky image (float32, (height, width,
+    4), alpha 1): a smooth field of low-order waves, periodic in varphi, plus
+    small soft spots; a stand-in for the photographs the paper renders behind
+    the hole.  Texel (i, j) sits at varphi = 2 pi (i + 1/2) / width,
+    theta = pi (j + 1/2) / height."""
+    rng = np.random.default_rng(seed)
+    ph = 2 * np.pi * (np.arange(width) + 0.5) / width
+    th = np.pi * (np.arange(height) + 0.5) / height
+    P, T = np.meshgrid(ph, th)
+    img = np.zeros((height, width, 4))
+    for _ in range(terms):
+        m = int(rng.integers(1, 6))          # integer waves in varphi: periodic
+        n = float(rng.uniform(0.5, 4.0))
+        amp = rng.uniform(0.05, 0.15, 3)
+        wave = np.cos(m * P + rng.uniform(0, 2 * np.pi)) * np.sin(n * T + rng.uniform(0, 2 * np.pi))
+        img[..., :3] += amp * wave[..., None]
+    # soft spots ("stars"), a few texels wide
+    for _ in range(stars):
+        i, j = int(rng.integers(0, width)), int(rng.integers(0, height))
+        rad = rng.uniform(1.5, 3.0)
+        c = rng.uniform(0.2, 0.6, 3)
+        i0, i1 = max(j - 8, 0), min(j + 9, height)
+        di = (np.arange(width) - i + width // 2) % width - width // 2
+        dj = np.arange(i0, i1) - j
+        g = np.exp(-(dj[:, None] ** 2 + di[None, :] ** 2) / (2 * rad * rad))
+        img[i0:i1, :, :3] += g[..., None] * c
+    img[..., :3] = np.clip(0.35 + img[..., :3], 0.0, 1.0)
+    img[..., 3] = 1.0
+    return img.astype(np.float32)
 
 
 # -- random ray sets -----------------------------------------------------------

@@ -26,7 +26,7 @@ def bh():
 
 def ref_scene(ref, s: inputs.Scene):
     return ref.scene(s.M, r_sky=s.r_sky, disk=s.disk, disk_power=s.disk_power,
-                     checker_deg=s.checker_deg)
+                     checker_deg=s.checker_deg, sky_tex=s.sky_tex)
 
 
 def ref_camera(ref, c: inputs.Camera):
@@ -254,3 +254,32 @@ def test_samples_per_pixel(bh, ref, precision):
     rgba1, _ = gpu_render(bh, f, p, samples_side=1)
     rgba0, _ = gpu_render(bh, f, p)
     np.testing.assert_array_equal(rgba1, rgba0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_textured_sky(bh, ref, precision):
+    """Equirectangular sky image with bilinear filtering: rays as for the
+    checker; sky colours within the image's largest texel step times the
+    texel displacement that the path's exit-angle bound allows."""
+    from parity import TOL
+    tex = inputs.sky_texture(256, 128, seed=3)
+    sc = inputs.Scene(M=1.0, r_sky=1000.0, disk=(6.0, 20.0), sky_tex=tex)
+    f = inputs.Frame(inputs.Camera(30.0, 75.0, 20.0, 60.0, 48, 32), sc)
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    rgba, out = gpu_render(bh, f, p)
+    r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, sc))
+    compare(r_rays, out, sc, precision)
+    t = TOL[precision]
+    rc, gc = r_rays.cls.astype(int), out["cls"].astype(int)
+    R, G = r_rgba.reshape(-1, 4).astype(np.float64), rgba.reshape(-1, 4).astype(np.float64)
+    sky = (rc == 0) & (gc == 0) & ~(np.abs(r_rays.b - B_CRIT) < 0.05)
+    s_ = r_rays.exit_dir[sky]
+    sin_t = np.maximum(np.hypot(s_[:, 0], s_[:, 1]), 1e-3)
+    step = max(np.abs(np.diff(tex, axis=1)).max(), np.abs(np.diff(tex, axis=0)).max())
+    H_t, W_t = tex.shape[:2]
+    tol = step * (W_t / (2 * np.pi) / sin_t + H_t / np.pi) * t["angle"] + 2e-6
+    d = np.abs(R[sky] - G[sky]).max(axis=1)
+    assert sky.sum() > 500
+    assert np.all(d <= tol), (d.max(), d[np.argmax(d / tol)], tol[np.argmax(d / tol)])
+    other = (rc == gc) & (rc == 1)
+    np.testing.assert_array_equal(G[other], R[other])

@@ -423,3 +423,75 @@ def test_caps_give_unresolved(ref):
     out = ref.trace_rays(o, d, ref.scene(M), ref.options(max_steps=5))
     assert out.cls[0] == ref.UNRESOLVED
     assert out.n_acc[0] + out.n_rej[0] == 5
+
+
+# -- equirectangular sky image: bilinear filtering --------------------------
+
+def _tex(W=16, H=8, seed=0):
+    return np.random.default_rng(seed).uniform(0, 1, (H, W, 4)).astype(np.float32)
+
+
+def test_sky_texture_texel_centres(ref):
+    """At a texel centre the sample is that texel."""
+    t = _tex()
+    H, W = t.shape[:2]
+    sc = ref.scene(1.0, sky_tex=t)
+    for j, i in [(0, 0), (3, 7), (7, 15), (5, 2)]:
+        got = ref.sky_sample(sc, math.pi * (j + 0.5) / H, 2 * math.pi * (i + 0.5) / W)
+        np.testing.assert_allclose(got, t[j, i], atol=1e-12)
+
+
+def test_sky_texture_reproduces_bilinear_functions(ref):
+    """A texture linear in (column, row) is reproduced exactly between texel
+    centres (away from the varphi seam and the clamped pole half-rows)."""
+    H, W = 8, 16
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    a = np.array([0.1, 0.2, -0.3, 1.0]); bi = np.array([0.01, -0.02, 0.03, 0.0])
+    cj = np.array([0.05, 0.04, -0.01, 0.0]); dij = np.array([0.002, 0.0, 0.001, 0.0])
+    t = (a + bi * ii[..., None] + cj * jj[..., None] + dij * (ii * jj)[..., None]).astype(np.float64)
+    t32 = t.astype(np.float32)
+    sc = ref.scene(1.0, sky_tex=t32)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        u = rng.uniform(0.0, W - 1.0)  # continuous texel coordinates, centres at integers
+        v = rng.uniform(0.0, H - 1.0)
+        want = a + bi * u + cj * v + dij * u * v
+        # the texture holds float32 roundings of the exact values: compare with them
+        i0, j0 = int(u), int(v)
+        fu, fv = u - i0, v - j0
+        q = t32.astype(np.float64)  # the stored texels, interpolated in FP64
+        want32 = ((1 - fv) * ((1 - fu) * q[j0, i0] + fu * q[j0, i0 + 1])
+                  + fv * ((1 - fu) * q[j0 + 1, i0] + fu * q[j0 + 1, i0 + 1]))
+        got = ref.sky_sample(sc, math.pi * (v + 0.5) / H, 2 * math.pi * (u + 0.5) / W)
+        np.testing.assert_allclose(got, want32, atol=1e-12)
+        np.testing.assert_allclose(got, want, atol=1e-6)
+
+
+def test_sky_texture_wraps_in_varphi_and_clamps_at_the_poles(ref):
+    t = _tex(seed=2)
+    H, W = t.shape[:2]
+    sc = ref.scene(1.0, sky_tex=t)
+    # across the seam: between the last column and the first
+    fu, j = 0.3, 4
+    got = ref.sky_sample(sc, math.pi * (j + 0.5) / H, 2 * math.pi * (W - 0.5 + fu) / W)
+    np.testing.assert_allclose(got, (1 - fu) * t[j, W - 1] + fu * t[j, 0], atol=1e-12)
+    # just past varphi = 0 from below is the same point as just below 2 pi
+    np.testing.assert_allclose(ref.sky_sample(sc, 1.0, 2 * math.pi - 1e-9),
+                               ref.sky_sample(sc, 1.0, 0.0), atol=1e-6)
+    # within half a row of a pole only that row contributes
+    i, fu = 5, 0.25
+    got = ref.sky_sample(sc, 0.1 * math.pi / H, 2 * math.pi * (i + 0.5 + fu) / W)
+    np.testing.assert_allclose(got, (1 - fu) * t[0, i] + fu * t[0, i + 1], atol=1e-12)
+    got = ref.sky_sample(sc, math.pi * (1 - 0.1 / H), 2 * math.pi * (i + 0.5 + fu) / W)
+    np.testing.assert_allclose(got, (1 - fu) * t[H - 1, i] + fu * t[H - 1, i + 1], atol=1e-12)
+
+
+def test_textured_sky_shading_uses_the_exit_direction(ref):
+    t = _tex(seed=3)
+    sc = ref.scene(1.0, sky_tex=t)
+    th, ph = 1.1, 4.0
+    s = [math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)]
+    np.testing.assert_allclose(ref.shade(sc, ref.SKY, s, 0.0), ref.sky_sample(sc, th, ph), atol=1e-6)
+    # disk and captured rays ignore the sky image
+    sc_d = ref.scene(1.0, disk=(6.0, 20.0), sky_tex=t)
+    np.testing.assert_allclose(ref.shade(sc_d, ref.CAPTURED, s, 0.0), [0, 0, 0, 1])
