@@ -118,6 +118,12 @@ typedef struct {
     int    batch_groups;     /* batches: consecutive request groups traced one after
                                 another (1 = one launch sequence for all); 0 = auto:
                                 about 64M rays per group                             */
+    double fixed_eps;        /* > 0: the paper's fixed-step mode (FP64 only): points
+                                about fixed_eps apart (absolute length) along the ray,
+                                one Dormand-Prince step each with no error control,
+                                disk / horizon / sky hits on the straight chords
+                                between consecutive points.  0: adaptive steps with
+                                events located on the curve (the default)            */
     const struct bh_surrogate* surrogate; /* FP32 renders only: route eligible rays to this
                                 trained network (NULL = off; see bh_surrogate_*)     */
 } bh_options;

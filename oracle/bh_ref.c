@@ -112,6 +112,7 @@ void bhr_default_options(bhr_options* opt)
     opt->hmax = 1.0;
     opt->max_phi = 8.0 * PI;
     opt->max_steps = 1000000;
+    opt->fixed_eps = 0.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -167,6 +168,72 @@ static void set_end(ray_result* res, int cls, double phi, const double e1[3], co
     res->cls = cls;
     res->phi_end = phi;
     for (int k = 0; k < 3; ++k) res->exit_dir[k] = cos(phi) * e1[k] + sin(phi) * e2[k];
+}
+
+/* Paper mode (Sec. "Approximating the trajectory of a light ray as a
+ * piecewise function", Sec. "Using GSL for ODE approximation", Fig.
+ * "nextpoint"): the ray is a sequence of points about eps apart.  From the
+ * point at (u, w, phi) the azimuth advances by the angle that a straight
+ * segment of length eps along the ray's current direction subtends at the
+ * hole -- the direction has radial and tangential components proportional
+ * to (-w, u), so dphi = atan2(eps u^2, sqrt(u^2 + w^2) - eps u w) -- with one
+ * Dormand-Prince step over dphi and no error control.  The scene is intersected with the straight
+ * chord between consecutive points, in order: the disk plane z = 0 (inside
+ * r_in <= |Q| <= r_out), the horizon (the new point inside r = 2M), the sky
+ * sphere (|Q| = r_sky on the chord).  In-plane coordinates: a point at
+ * (r, phi) is r (cos phi e1 + sin phi e2); its height is r zeta(phi) with
+ * zeta(phi) = e1z cos(phi) + e2z sin(phi). */
+static void trace_paper(const bhr_scene* sc, const bhr_options* opt, const double e1[3],
+                        const double e2[3], double u0, double w0, int disk_on, ray_result* res)
+{
+    const double M = sc->M, R = sc->r_sky, u_sky = 1.0 / R, eps = opt->fixed_eps;
+    double u = u0, w = w0, phi = 0.0;
+    double x = 1.0 / u0, y = 0.0;        /* current point, in-plane coordinates */
+    double z = x * e1[2];                /* its height */
+    for (;;) {
+        if (res->n_acc >= opt->max_steps || phi > opt->max_phi) {
+            set_end(res, BHR_UNRESOLVED, phi, e1, e2);
+            return;
+        }
+        const double h = atan2(eps * u * u, sqrt(u * u + w * w) - eps * u * w);
+        double un, wn, eu, ew;
+        dopri5_step(M, u, w, h, &un, &wn, &eu, &ew);
+        ++res->n_acc;
+        const double phin = phi + h;
+        const double rn = un > 0.0 ? 1.0 / un : 1e300;
+        const double xn = rn * cos(phin), yn = rn * sin(phin);
+        const double zn = rn * (e1[2] * cos(phin) + e2[2] * sin(phin));
+        if (disk_on && ((z < 0.0 && zn >= 0.0) || (z > 0.0 && zn <= 0.0))) {
+            const double t = z / (z - zn);
+            const double qx = x + t * (xn - x), qy = y + t * (yn - y);
+            const double rq = sqrt(qx * qx + qy * qy);
+            if (rq >= sc->disk_rin && rq <= sc->disk_rout) {
+                res->r_hit = rq;
+                set_end(res, BHR_DISK, phi + atan2(x * qy - y * qx, x * qx + y * qy), e1, e2);
+                return;
+            }
+        }
+        if (M > 0.0 && 2.0 * M * un >= 1.0) {
+            set_end(res, BHR_CAPTURED, phin, e1, e2);
+            return;
+        }
+        if (un <= u_sky) {
+            /* |P + t (Pn - P)| = R with |P| < R: the root t in (0, 1] */
+            const double dx = xn - x, dy = yn - y;
+            const double qa = dx * dx + dy * dy, qb = 2.0 * (x * dx + y * dy);
+            const double qc = x * x + y * y - R * R;
+            const double t = (-qb + sqrt(qb * qb - 4.0 * qa * qc)) / (2.0 * qa);
+            const double qx = x + t * dx, qy = y + t * dy;
+            set_end(res, BHR_SKY, phi + atan2(x * qy - y * qx, x * qx + y * qy), e1, e2);
+            return;
+        }
+        u = un;
+        w = wn;
+        phi = phin;
+        x = xn;
+        y = yn;
+        z = zn;
+    }
 }
 
 static void trace_one(const double o[3], const double d_in[3], const bhr_scene* sc,
@@ -244,6 +311,11 @@ static void trace_one(const double o[3], const double d_in[3], const bhr_scene* 
                 if (phi_k <= 0.0) phi_k += PI; /* first root in (0, pi] */
             }
         }
+    }
+
+    if (opt->fixed_eps > 0.0) {
+        trace_paper(sc, opt, e1, e2, u0, w0, sc->has_disk && hypot(e1[2], e2[2]) > 1e-15, res);
+        return;
     }
 
     const double u_sky = 1.0 / R;

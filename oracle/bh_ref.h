@@ -81,6 +81,10 @@ typedef struct {
     double hmax;         /* largest step in phi                               */
     double max_phi;      /* sweep cap -> UNRESOLVED                           */
     int    max_steps;    /* cap on step attempts -> UNRESOLVED                */
+    double fixed_eps;    /* > 0: the paper's fixed-step mode -- points about
+                            fixed_eps apart (absolute length), one Dormand-Prince
+                            step each, scene hits on the chords between them;
+                            0: adaptive steps with events on the curve          */
 } bhr_options;
 
 /* Structure-of-arrays output, length n; any pointer may be NULL. */

@@ -48,7 +48,8 @@ class Camera(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
-                ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int)]
+                ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
+                ("fixed_eps", C.c_double)]
 
 
 class Out(C.Structure):
@@ -113,10 +114,12 @@ def camera(r, incl_deg, azim_deg, fov_deg, width, height) -> Camera:
     return Camera(r, incl_deg, azim_deg, fov_deg, int(width), int(height))
 
 
-def options(rtol=1e-10, atol=0.0, h0=1e-2, hmax=1.0, max_phi=None, max_steps=1000000) -> Options:
+def options(rtol=1e-10, atol=0.0, h0=1e-2, hmax=1.0, max_phi=None, max_steps=1000000,
+            fixed_eps=0.0) -> Options:
     o = Options()
     lib().bhr_default_options(C.byref(o))
     o.rtol, o.atol, o.h0, o.hmax, o.max_steps = rtol, atol, h0, hmax, max_steps
+    o.fixed_eps = fixed_eps
     if max_phi is not None:
         o.max_phi = max_phi
     return o

@@ -42,7 +42,7 @@ class Options(C.Structure):
                 ("h0_fp32", C.c_double),
                 ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
                 ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
-                ("samples_side", C.c_int), ("batch_groups", C.c_int),
+                ("samples_side", C.c_int), ("batch_groups", C.c_int), ("fixed_eps", C.c_double),
                 ("surrogate", C.c_void_p)]
 
 

@@ -182,6 +182,10 @@ bh_status check_opt(const bh_options* o) {
         !finite_pos(o->max_phi))
         return fail(BH_ERR_ARG, "h0, h0_fp32, hmax and max_phi must be > 0");
     if (o->max_steps < 1) return fail(BH_ERR_ARG, "max_steps must be >= 1");
+    if (!(isfinite(o->fixed_eps) && o->fixed_eps >= 0.0))
+        return fail(BH_ERR_ARG, "fixed_eps must be finite and >= 0");
+    if (o->fixed_eps > 0.0 && (o->precision != BH_FP64 || o->surrogate))
+        return fail(BH_ERR_UNSUPPORTED, "the fixed-step mode runs in FP64 without the surrogate");
     if (o->samples_side < 0 || o->samples_side > 16)
         return fail(BH_ERR_ARG, "samples_side must be in [0, 16]");
     if (o->grid_blocks < 0 || o->chunk < 0 || o->batch_groups < 0)
@@ -334,8 +338,11 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
         if (e != hipSuccess) return hip_fail(e, "surrogate");
     }
     t = timing_begin(1, stream);
-    e = bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w, ws->cus,
-                             opt->grid_blocks, auto_chunk(opt), stream);
+    e = opt->fixed_eps > 0.0
+            ? bh::launch_integrate_paper(src.n, explicit_u0, u0_uniform, sc, tol, opt->fixed_eps, w,
+                                         ws->cus, stream)
+            : bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w,
+                                   ws->cus, opt->grid_blocks, auto_chunk(opt), stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "integrate");
     t = timing_begin(2, stream);
@@ -499,6 +506,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     if (st != BH_OK) return st;
     if (opt->surrogate) return fail(BH_ERR_UNSUPPORTED, "batches do not route to the surrogate");
     if (opt->samples_side > 1) return fail(BH_ERR_UNSUPPORTED, "batches trace one ray per pixel");
+    if (opt->fixed_eps > 0.0) return fail(BH_ERR_UNSUPPORTED, "batches use adaptive steps");
     std::vector<bh::ReqDev> req(n);
     std::vector<bh::BatchConst> bc(n);
     std::vector<int64_t> off(n + 1, 0);

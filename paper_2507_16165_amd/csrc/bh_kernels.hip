@@ -674,6 +674,89 @@ k_integrate_fp32_batch(IntegArgs a, int band_blocks) {
 }
 
 // ---------------------------------------------------------------------------
+// The paper's fixed-step mode (FP64).  The ray is followed as a sequence of
+// points about eps apart: from (u, w, phi) the azimuth advances by the angle
+// a straight segment of length eps along the ray's current direction
+// (radial and tangential components proportional to (-w, u)) subtends at the
+// hole, dphi = atan2(eps u^2, sqrt(u^2 + w^2) - eps u w), with one
+// Dormand-Prince step and no error control.  Scene hits are found on the
+// straight chord between consecutive points (in-plane coordinates
+// x = r cos phi, y = r sin phi): the disk plane where the height, which is
+// proportional to r sin(phi_1 - phi), changes sign (a hit if the chord point
+// lies within [r_in, r_out]); the horizon when the new point is inside
+// r = 2M; the sky sphere where the chord reaches r_sky.  One thread per ray
+// (rays take hundreds to thousands of steps; neighbouring pixels take about
+// as many).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_integrate_paper(IntegArgs a, double eps) {
+    const double M = a.sc.M, M3 = 3.0 * a.sc.M, u_sky = a.sc.u_sky;
+    const double R = a.sc.r_sky;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double2 rec = a.w.rec[i];
+        if (!(rec.x == rec.x)) continue;  // finished at set-up
+        const double phi1 = rec.y;
+        const bool disk_on = a.sc.has_disk && phi1 < 1e300;
+        double u = a.u0 ? a.u0[i] : a.u0_uniform, w = rec.x, g = g_of(M3, u), phi = 0.0;
+        double x = 1.0 / u, y = 0.0, z = disk_on ? x * sin(phi1) : 0.0;
+        int steps = 0;
+        uint8_t cls = UNRESOLVED;
+        double pe = 0.0, rh = 0.0;
+        for (;;) {
+            if (steps >= a.tol.max_steps || phi > a.tol.max_phi) {
+                pe = phi;
+                break;
+            }
+            const double h = atan2(eps * u * u, sqrt(fma(u, u, w * w)) - eps * u * w);
+            double un, wn, gn, eu, ew;
+            dp45<double>(M3, u, w, g, h, un, wn, gn, eu, ew);
+            ++steps;
+            const double phin = phi + h;
+            const double rn = un > 0.0 ? 1.0 / un : 1e300;
+            double sn, cn;
+            sincos(phin, &sn, &cn);
+            const double xn = rn * cn, yn = rn * sn;
+            const double zn = disk_on ? rn * sin(phi1 - phin) : 0.0;
+            if (disk_on && ((z < 0.0 && zn >= 0.0) || (z > 0.0 && zn <= 0.0))) {
+                const double t = z / (z - zn);
+                const double qx = fma(t, xn - x, x), qy = fma(t, yn - y, y);
+                const double rq = sqrt(fma(qx, qx, qy * qy));
+                if (rq >= a.sc.rin && rq <= a.sc.rout) {
+                    cls = DISK;
+                    rh = rq;
+                    pe = phi + atan2(x * qy - y * qx, fma(x, qx, y * qy));
+                    break;
+                }
+            }
+            if (M > 0.0 && 2.0 * M * un >= 1.0) {
+                cls = CAPTURED;
+                pe = phin;
+                break;
+            }
+            if (un <= u_sky) {
+                const double dx = xn - x, dy = yn - y;
+                const double qa = fma(dx, dx, dy * dy), qb = 2.0 * fma(x, dx, y * dy);
+                const double qc = fma(x, x, y * y) - R * R;
+                const double t = (-qb + sqrt(fma(qb, qb, -4.0 * qa * qc))) / (2.0 * qa);
+                const double qx = fma(t, dx, x), qy = fma(t, dy, y);
+                cls = SKY;
+                pe = phi + atan2(x * qy - y * qx, fma(x, qx, y * qy));
+                break;
+            }
+            u = un;
+            w = wn;
+            g = gn;
+            phi = phin;
+            x = xn;
+            y = yn;
+            z = zn;
+        }
+        a.w.res[i] = make_double2(pe, rh);
+        a.w.clst[i] = (int32_t)cls | (steps << 3);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Shading and output.
 // ---------------------------------------------------------------------------
 // Mapping back to 3-D and shading of workspace ray i; px (may be NULL)
@@ -1117,6 +1200,23 @@ hipError_t launch_shade_samples(const Source& src, const DevScene& sc, const Wor
     if (npx == 0) return hipSuccess;
     if (precision == 1) k_shade_samples<true><<<blocks_for(npx), kBlock, 0, s>>>(src, sc, w, rgba, out, n);
     else k_shade_samples<false><<<blocks_for(npx), kBlock, 0, s>>>(src, sc, w, rgba, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_paper(int64_t n, bool explicit_u0, double u0_uniform,
+                                  const DevScene& sc, const DevTol& tol, double eps,
+                                  const Work& w, int cus, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    IntegArgs a{};
+    a.n = n;
+    a.u0 = explicit_u0 ? w.u0 : nullptr;
+    a.u0_uniform = u0_uniform;
+    a.sc = sc;
+    a.tol = tol;
+    a.w = w;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > (int64_t)cus * 16) g = (int64_t)cus * 16;
+    k_integrate_paper<<<(unsigned)g, kBlock, 0, s>>>(a, eps);
     return hipGetLastError();
 }
 

@@ -72,6 +72,8 @@ def test_render_rejects_null_and_bad_options():
     assert _render(cam, sc, api.options(samples_side=17)) == api.BH_ERR_ARG
     assert _render(cam, sc, api.options(samples_side=-1)) == api.BH_ERR_ARG
     assert _render(cam, sc, api.options(batch_groups=-1)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(fixed_eps=-1.0)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(fixed_eps=0.5, precision=api.FP32)) == api.BH_ERR_UNSUPPORTED
     L = api.lib()
     assert L.bh_render(None, None, None, None, None, None) == api.BH_ERR_ARG
     assert L.bh_default_options(None) == api.BH_ERR_ARG
@@ -125,5 +127,7 @@ def test_batch_argument_checks():
     assert L.bh_batch_create(reqs, 1, C.byref(o), 0, C.byref(h)) == api.BH_ERR_ARG
     o2 = api.options(samples_side=2)
     assert L.bh_batch_create(reqs, 1, C.byref(o2), 0, C.byref(h)) == api.BH_ERR_UNSUPPORTED
+    o3 = api.options(fixed_eps=0.5)
+    assert L.bh_batch_create(reqs, 1, C.byref(o3), 0, C.byref(h)) == api.BH_ERR_UNSUPPORTED
     assert L.bh_batch_launch(None, None) == api.BH_ERR_ARG
     assert L.bh_batch_destroy(None) == api.BH_OK

@@ -283,3 +283,21 @@ def test_textured_sky(bh, ref, precision):
     assert np.all(d <= tol), (d.max(), d[np.argmax(d / tol)], tol[np.argmax(d / tol)])
     other = (rc == gc) & (rc == 1)
     np.testing.assert_array_equal(G[other], R[other])
+
+
+@pytest.mark.parametrize("M,disk", [(1.0, (6.0, 20.0)), (0.0, (2.0, 12.0))])
+def test_paper_fixed_step_mode(bh, ref, M, disk):
+    """The paper's fixed-step mode (points ~eps apart, hits on chords) against
+    the oracle's, both FP64: the same classes, exit directions and hit radii
+    to the FP64 bounds, and the same number of steps per ray."""
+    eps = 0.5
+    f = inputs.Frame(inputs.Camera(30.0, 80.0, 10.0, 60.0, 40, 30),
+                     inputs.Scene(M=M, r_sky=1000.0, disk=disk))
+    rgba, out = gpu_render(bh, f, bh.FP64, fixed_eps=eps)
+    r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene),
+                                ref.options(fixed_eps=eps))
+    compare(r_rays, out, f.scene, "fp64")
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, "fp64")
+    integ = r_rays.n_acc > 0
+    assert np.abs(out["steps"][integ] - r_rays.n_acc[integ]).max() <= 1
+    assert out["steps"][integ].mean() > 100  # many short steps, as the paper takes them

@@ -495,3 +495,43 @@ def test_textured_sky_shading_uses_the_exit_direction(ref):
     # disk and captured rays ignore the sky image
     sc_d = ref.scene(1.0, disk=(6.0, 20.0), sky_tex=t)
     np.testing.assert_allclose(ref.shade(sc_d, ref.CAPTURED, s, 0.0), [0, 0, 0, 1])
+
+
+# -- the paper's fixed-step mode: points ~eps apart, hits on chords ----------
+
+def _paper_errors(ref, M, disk, eps_list):
+    cam = ref.camera(30, 80, 0, 60, 32, 24)
+    sc = ref.scene(M, r_sky=1000.0, disk=disk)
+    _, a = ref.render(cam, sc, ref.options(rtol=1e-13))
+    out = []
+    for eps in eps_list:
+        _, p = ref.render(cam, sc, ref.options(fixed_eps=eps))
+        assert np.array_equal(a.cls, p.cls)
+        d = a.cls == 2
+        s = a.cls == 0
+        ang = np.arctan2(np.linalg.norm(np.cross(a.exit_dir[s], p.exit_dir[s]), axis=1),
+                         np.sum(a.exit_dir[s] * p.exit_dir[s], 1))
+        out.append((np.abs(p.r_hit[d] / a.r_hit[d] - 1.0).max(), ang.max(), p.n_acc.mean()))
+    return out
+
+
+def test_paper_mode_chords_are_second_order_in_curved_space(ref):
+    """With M > 0 the disk-hit radius error comes from the chord's sagitta:
+    it falls by ~4 when eps halves; the exit direction converges fast (the
+    chord is nearly straight far out); points are ~eps apart, so the number
+    of steps doubles."""
+    e = _paper_errors(ref, 1.0, (6.0, 20.0), [0.5, 0.25, 0.125])
+    for k in range(2):
+        assert 3.0 < e[k][0] / e[k + 1][0] < 5.5, e
+        assert 1.8 < e[k + 1][2] / e[k][2] < 2.2, e
+    assert e[2][1] < 1e-10
+
+
+def test_paper_mode_chords_are_exact_in_flat_space(ref):
+    """With M = 0 the ray is a straight line, so its chords are exact: only
+    the integration error of the (large) steps remains, and it falls much
+    faster than the sagitta's eps^2."""
+    e = _paper_errors(ref, 0.0, (2.0, 12.0), [0.5, 0.25, 0.125])
+    for k in range(2):
+        assert e[k][0] / e[k + 1][0] > 16.0, e
+    assert e[2][0] < 1e-7 and e[2][1] < 1e-10
