@@ -80,6 +80,8 @@ def main() -> int:
                     help="skip the surrogate leg (training and the surrogate render)")
     ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving leg")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the fixed-step (paper) mode sweep")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the all-pixel comparison of the fast path with the FP64 kernel")
     ap.add_argument("--batch-requests", type=int, default=512)
@@ -222,6 +224,8 @@ def main() -> int:
 
     if not args.no_accuracy:
         line["accuracy_all_pixels"] = accuracy_leg(frames, api, torch)
+    if not args.no_paper:
+        line["paper_mode_sweep"] = paper_leg(frames[:2], api, torch)
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value, step)
     if not args.no_batch:
@@ -315,6 +319,69 @@ def accuracy_leg(frames, api, torch):
             "p99_exit_angle_rad_upper": 10 ** ((p99_bin + 1) / 10.0 - 20.0),
             "max_disk_r_rel": rr_max,
             "colour_mismatch_fraction": colour_bad / max(colour_n, 1)}
+
+
+def paper_leg(frames, api, torch):
+    """The paper's own scheme on two 4K frames: points eps*M apart, one step
+    each, hits on chords (FP64), for a few eps; throughput and the largest
+    exit-direction and disk-radius errors against the adaptive FP64 kernel
+    (rays of equal class outside the critical band).  The adaptive FP32 + band
+    and FP64 paths on the same frames are the other points of the trade-off."""
+    import math
+    W, H = frames[0].camera.width, frames[0].camera.height
+    fields = ("cls", "b", "exit_dir", "r_hit", "steps")
+    buf = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    refs = [api.render(f.camera, f.scene, api.options(precision=api.FP64), fields=fields)[1]
+            for f in frames]
+
+    def measure(opt_of):
+        for f in frames:
+            api.render(f.camera, f.scene, opt_of(f), rgba=buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in frames:
+            api.render(f.camera, f.scene, opt_of(f), rgba=buf)
+        torch.cuda.synchronize()
+        mrays = len(frames) * W * H / (time.perf_counter() - t0) / 1e6
+        ang_max, rr_max, rr_far, worst_db, steps, edge_diff = 0.0, 0.0, 0.0, None, 0, 0
+        for f, b in zip(frames, refs):
+            _, a = api.render(f.camera, f.scene, opt_of(f), rgba=buf, fields=fields)
+            steps += int(a["steps"].to(torch.int64).sum().item())
+            band = (b["b"] - 3.0 * math.sqrt(3.0) * f.scene.M).abs() < 0.05 * f.scene.M
+            same = (a["cls"] == b["cls"]) & ~band
+            sky = same & (b["cls"] == 0)
+            u, v = a["exit_dir"][sky], b["exit_dir"][sky]
+            ang = torch.atan2(torch.linalg.cross(u, v).norm(dim=1), (u * v).sum(1))
+            ang_max = max(ang_max, float(ang.max().item()))
+            dsk = same & (b["cls"] == 2)
+            # disk-edge zone: a reference hit within 1% of an edge can be
+            # missed by the chord (and the ray then hits at a later crossing)
+            rin, rout = f.scene.disk
+            edge = ((b["r_hit"] - rin).abs() < 0.01 * rin) | ((b["r_hit"] - rout).abs() < 0.01 * rout)
+            edge_diff += int((dsk & edge & ((a["r_hit"] / b["r_hit"] - 1).abs() > 1e-2)).sum().item())
+            dsk = dsk & ~edge
+            if bool(dsk.any()):
+                rr = (a["r_hit"][dsk] / b["r_hit"][dsk] - 1).abs()
+                db = (b["b"][dsk] - 3.0 * math.sqrt(3.0) * f.scene.M) / f.scene.M
+                k = int(rr.argmax().item())
+                if float(rr[k].item()) > rr_max:
+                    rr_max, worst_db = float(rr[k].item()), float(db[k].item())
+                far = db.abs() >= 0.5
+                if bool(far.any()):
+                    rr_far = max(rr_far, float(rr[far].max().item()))
+        return {"mrays_per_s": round(mrays, 1), "max_exit_angle_rad": ang_max,
+                "max_disk_r_rel": rr_max, "worst_disk_ray_b_minus_bc_M": worst_db,
+                "max_disk_r_rel_beyond_0.5M": rr_far,
+                "edge_zone_rays_hitting_another_crossing": edge_diff,
+                "steps_per_ray": round(steps / (len(frames) * W * H), 1)}
+
+    out = {"frames": len(frames), "reference": "adaptive FP64 kernel (rtol 1e-10)"}
+    for eps in (8.0, 2.0, 0.5):
+        log(f"paper mode: eps = {eps} M")
+        out[f"eps_{eps:g}M"] = measure(lambda f, e=eps: api.options(precision=api.FP64,
+                                                                  fixed_eps=e * f.scene.M))
+    out["adaptive_fp32_band"] = measure(lambda f: api.options(precision=api.FP32))
+    return out
 
 
 FLOP_PER_SUR_RAY = 66560     # 2 x (2*128 + 128*128 + 128*128 + 128*2) multiply-adds
