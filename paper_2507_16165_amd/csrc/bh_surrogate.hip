@@ -419,11 +419,25 @@ __device__ inline void mlp_tiles(const bf16* __restrict__ pk, const float* __res
     }
 }
 
-// Copies the inference pack into LDS (coalesced, 16 B per thread step).
+// Copies the inference pack into LDS (kInferThreads threads, coalesced 16 B
+// per thread and step).  All of a thread's loads are issued before its LDS
+// stores, so the copy costs about one memory latency, not one per step.
 __device__ inline void load_pack(const void* src, void* lds) {
+    constexpr int kN = kPackBytes / 16;
+    constexpr int kPer = (kN + kInferThreads - 1) / kInferThreads;
     const int4* s = reinterpret_cast<const int4*>(src);
     int4* d = reinterpret_cast<int4*>(lds);
-    for (int i = threadIdx.x; i < kPackBytes / 16; i += blockDim.x) d[i] = s[i];
+    int4 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + k * kInferThreads;
+        if (i < kN) v[k] = s[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + k * kInferThreads;
+        if (i < kN) d[i] = v[k];
+    }
     __syncthreads();
 }
 
@@ -561,14 +575,13 @@ struct SurEntry {
     bool valid;
 };
 
+// `slice` is the caller's last slice (tiles of a wavefront only increase):
+// it walks forward to the last slice with first[s] <= t.
 __device__ inline SurEntry sur_entry(const int* cnt, const int* first, int64_t slice_cap,
-                                     int64_t t, int lane) {
-    int lo = 0, hi = kSurSlices - 1;  // last slice with first[s] <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (first[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
+                                     int64_t t, int lane, int& slice) {
+    int lo = slice;
+    while (lo + 1 < kSurSlices && first[lo + 1] <= t) ++lo;
+    slice = lo;
     const int64_t j = (t - first[lo]) * 32 + lane;
     const bool valid = j < cnt[lo];
     return {lo * slice_cap + (valid ? j : 0), valid};
@@ -600,10 +613,10 @@ void k_sur_render(const void* __restrict__ pack, SurRender a) {
     const int64_t nw = (int64_t)gridDim.x * wpb;
     int64_t t = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
     SurEntry e{0, false};
-    int id = 0;
+    int id = 0, slice = 0;
     double2 rec = make_double2(10.0, 0.0);
     if (t < tiles) {
-        e = sur_entry(s_cnt, s_first, a.slice_cap, t, l & 31);
+        e = sur_entry(s_cnt, s_first, a.slice_cap, t, l & 31, slice);
         id = a.w.qsur[e.slot];
         rec = a.w.qsurrec[e.slot];
     }
@@ -613,7 +626,7 @@ void k_sur_render(const void* __restrict__ pack, SurRender a) {
         int idn = 0;
         double2 recn = make_double2(10.0, 0.0);
         if (t + nw < tiles) {
-            en = sur_entry(s_cnt, s_first, a.slice_cap, t + nw, l & 31);
+            en = sur_entry(s_cnt, s_first, a.slice_cap, t + nw, l & 31, slice);
             idn = a.w.qsur[en.slot];
             recn = a.w.qsurrec[en.slot];
         }

@@ -26,12 +26,16 @@ def mixed_frames():
     out = []
     sizes = [(33, 17), (64, 64), (1, 1), (128, 96), (200, 150), (57, 301), (96, 96), (250, 250)]
     rng = np.random.default_rng(12)
+    tex = inputs.sky_texture(128, 64, seed=9)
     for k, (w, h) in enumerate(sizes):
         M = float(rng.uniform(0.5, 2.0))
         rho = float(rng.uniform(15.0, 120.0))
         disk = (6.0, 20.0) if k % 2 == 0 else None
         cam = inputs.Camera(rho * M, float(rng.uniform(0, 90)), float(rng.uniform(0, 360)), 60.0, w, h)
-        out.append(inputs.Frame(cam, inputs.scene_in_m(M, disk), f"m{k}"))
+        sc = inputs.scene_in_m(M, disk)
+        if k in (3, 6):  # two requests with a sky image instead of the checker
+            sc = inputs.Scene(M=sc.M, r_sky=sc.r_sky, disk=sc.disk, sky_tex=tex)
+        out.append(inputs.Frame(cam, sc, f"m{k}"))
     return out
 
 
