@@ -224,10 +224,15 @@ def main() -> int:
 
     if not args.no_accuracy:
         line["accuracy_all_pixels"] = accuracy_leg(frames, api, torch)
+    sweep = None
     if not args.no_paper:
-        line["paper_mode_sweep"] = paper_leg(frames[:2], api, torch)
+        sweep = Sweep(frames[:2], api, torch)
+        line["paper_mode_sweep"] = paper_leg(sweep, api)
     if not args.no_surrogate:
-        line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value, step)
+        line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value, step, sweep)
+        if sweep is not None:
+            line["paper_mode_sweep"]["adaptive_fp32_band_surrogate"] = line["surrogate"].pop("sweep_point")
+    
     if not args.no_batch:
         line["batch_serving"] = batch_leg(args, api, torch)
     if not args.no_cpu_baseline:
@@ -321,20 +326,28 @@ def accuracy_leg(frames, api, torch):
             "colour_mismatch_fraction": colour_bad / max(colour_n, 1)}
 
 
-def paper_leg(frames, api, torch):
-    """The paper's own scheme on two 4K frames: points eps*M apart, one step
-    each, hits on chords (FP64), for a few eps; throughput and the largest
-    exit-direction and disk-radius errors against the adaptive FP64 kernel
-    (rays of equal class outside the critical band).  The adaptive FP32 + band
-    and FP64 paths on the same frames are the other points of the trade-off."""
-    import math
-    W, H = frames[0].camera.width, frames[0].camera.height
-    fields = ("cls", "b", "exit_dir", "r_hit", "steps")
-    buf = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
-    refs = [api.render(f.camera, f.scene, api.options(precision=api.FP64), fields=fields)[1]
-            for f in frames]
+class Sweep:
+    """Accuracy against throughput on a few 4K frames: each point renders the
+    frames with some options, times them, and compares per-ray records with an
+    adaptive FP64 reference at rtol 1e-12 (rays of equal class outside the
+    critical band |b - b_c| < 0.05 M).  Exit directions of sky rays are
+    compared by angle; disk radii relative, outside a 1% zone at either disk
+    edge where a chord or a loose step can miss an edge hit."""
 
-    def measure(opt_of):
+    REF_RTOL = 1e-12
+    FIELDS = ("cls", "b", "exit_dir", "r_hit", "steps")
+
+    def __init__(self, frames, api, torch):
+        self.frames, self.api, self.torch = frames, api, torch
+        W, H = frames[0].camera.width, frames[0].camera.height
+        self.buf = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        self.refs = [api.render(f.camera, f.scene, api.options(precision=api.FP64, rtol=self.REF_RTOL),
+                                fields=self.FIELDS)[1] for f in frames]
+
+    def point(self, opt_of):
+        import math
+        api, torch, frames, buf = self.api, self.torch, self.frames, self.buf
+        W, H = frames[0].camera.width, frames[0].camera.height
         for f in frames:
             api.render(f.camera, f.scene, opt_of(f), rgba=buf)
         torch.cuda.synchronize()
@@ -343,19 +356,18 @@ def paper_leg(frames, api, torch):
             api.render(f.camera, f.scene, opt_of(f), rgba=buf)
         torch.cuda.synchronize()
         mrays = len(frames) * W * H / (time.perf_counter() - t0) / 1e6
-        ang_max, rr_max, rr_far, worst_db, steps, edge_diff = 0.0, 0.0, 0.0, None, 0, 0
-        for f, b in zip(frames, refs):
-            _, a = api.render(f.camera, f.scene, opt_of(f), rgba=buf, fields=fields)
+        ang_max, rr_max, rr_far, worst_db, steps, edge_diff, cls_diff = 0.0, 0.0, 0.0, None, 0, 0, 0
+        for f, b in zip(frames, self.refs):
+            _, a = api.render(f.camera, f.scene, opt_of(f), rgba=buf, fields=self.FIELDS)
             steps += int(a["steps"].to(torch.int64).sum().item())
             band = (b["b"] - 3.0 * math.sqrt(3.0) * f.scene.M).abs() < 0.05 * f.scene.M
+            cls_diff += int(((a["cls"] != b["cls"]) & ~band).sum().item())
             same = (a["cls"] == b["cls"]) & ~band
             sky = same & (b["cls"] == 0)
             u, v = a["exit_dir"][sky], b["exit_dir"][sky]
             ang = torch.atan2(torch.linalg.cross(u, v).norm(dim=1), (u * v).sum(1))
             ang_max = max(ang_max, float(ang.max().item()))
             dsk = same & (b["cls"] == 2)
-            # disk-edge zone: a reference hit within 1% of an edge can be
-            # missed by the chord (and the ray then hits at a later crossing)
             rin, rout = f.scene.disk
             edge = ((b["r_hit"] - rin).abs() < 0.01 * rin) | ((b["r_hit"] - rout).abs() < 0.01 * rout)
             edge_diff += int((dsk & edge & ((a["r_hit"] / b["r_hit"] - 1).abs() > 1e-2)).sum().item())
@@ -373,14 +385,28 @@ def paper_leg(frames, api, torch):
                 "max_disk_r_rel": rr_max, "worst_disk_ray_b_minus_bc_M": worst_db,
                 "max_disk_r_rel_beyond_0.5M": rr_far,
                 "edge_zone_rays_hitting_another_crossing": edge_diff,
+                "class_differences_outside_band": cls_diff,
                 "steps_per_ray": round(steps / (len(frames) * W * H), 1)}
 
-    out = {"frames": len(frames), "reference": "adaptive FP64 kernel (rtol 1e-10)"}
+
+def paper_leg(sweep, api):
+    """The paper's own scheme (points eps*M apart, one step each, hits on
+    chords; FP64) for a few eps, beside the adaptive FP64 path at three rtol
+    and FP32 + band at three rtol_fp32: the accuracy/throughput trade-off."""
+    out = {"frames": len(sweep.frames),
+           "reference": f"adaptive FP64 kernel (rtol {sweep.REF_RTOL:g})"}
     for eps in (8.0, 2.0, 0.5):
         log(f"paper mode: eps = {eps} M")
-        out[f"eps_{eps:g}M"] = measure(lambda f, e=eps: api.options(precision=api.FP64,
-                                                                  fixed_eps=e * f.scene.M))
-    out["adaptive_fp32_band"] = measure(lambda f: api.options(precision=api.FP32))
+        out[f"eps_{eps:g}M"] = sweep.point(lambda f, e=eps: api.options(precision=api.FP64,
+                                                                      fixed_eps=e * f.scene.M))
+    for rt in (1e-6, 1e-8, 1e-10):
+        log(f"sweep: adaptive FP64 rtol {rt:g}")
+        out[f"adaptive_fp64_rtol_{rt:g}"] = sweep.point(
+            lambda f, r=rt: api.options(precision=api.FP64, rtol=r))
+    for rt in (1e-4, 1e-5, 1e-6):
+        log(f"sweep: adaptive FP32 + band rtol_fp32 {rt:g}")
+        out[f"adaptive_fp32_band_rtol_{rt:g}"] = sweep.point(
+            lambda f, r=rt: api.options(precision=api.FP32, rtol_fp32=r))
     return out
 
 
@@ -388,7 +414,7 @@ FLOP_PER_SUR_RAY = 66560     # 2 x (2*128 + 128*128 + 128*128 + 128*2) multiply-
 PEAK_BF16_TFLOPS = 2500.0    # dense BF16 matrix-core peak
 
 
-def surrogate_leg(args, frames, bufs, api, torch, value_fast, step):
+def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None):
     """Trains the network on the GPU (4M escape-side + 1M capture-side FP64
     labels, Adam), builds its trust map, then renders the same frames with
     FP32 + band + surrogate.  Reports the throughput, the gain over the
@@ -437,8 +463,9 @@ def surrogate_leg(args, frames, bufs, api, torch, value_fast, step):
     sur_rays_launch = n_sur / len(frames)
     ach = (sur_rays_launch * FLOP_PER_SUR_RAY / (sur_ms / sur_n * 1e-3) / 1e12) if sur_n else 0.0
     value = rays / (ms * 1e-3) / 1e6
+    point = sweep.point(lambda f: opt) if sweep is not None else None
     sur.close()
-    return {
+    res = {
         "value": round(value, 2), "unit": "Mrays/s", "ms_per_step": round(ms, 4),
         "gain_vs_fp32_band": round(value / value_fast, 4),
         "share": round(n_sur / rays, 4),
@@ -456,6 +483,9 @@ def surrogate_leg(args, frames, bufs, api, torch, value_fast, step):
                      "flop_per_launch": sur_rays_launch * FLOP_PER_SUR_RAY,
                      "avg_launch_ms": round(sur_ms / sur_n, 4) if sur_n else None},
     }
+    if point is not None:
+        res["sweep_point"] = point
+    return res
 
 
 def batch_leg(args, api, torch):

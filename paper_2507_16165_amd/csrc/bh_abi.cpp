@@ -205,6 +205,7 @@ bh::DevScene dev_scene(const bh_scene* sc) {
     d.power = sc->has_disk ? sc->disk_power : 0.0;
     d.urin = sc->has_disk ? 1.0 / sc->disk_rin : 0.0;
     d.urout = sc->has_disk ? 1.0 / sc->disk_rout : 0.0;
+    d.uh = sc->M > 0.0 ? 1.0 / (2.0 * sc->M) : INFINITY;
     d.cell_rad = sc->checker_deg * kPi / 180.0;
     d.inv_cell = 1.0 / d.cell_rad;
     d.tex = reinterpret_cast<const float4*>(sc->sky_tex);
@@ -525,6 +526,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         bc[r].usky = req[r].sc.u_sky;
         bc[r].urin = req[r].sc.urin;
         bc[r].urout = req[r].sc.urout;
+        bc[r].uh = req[r].sc.uh;
         bc[r].u0 = 1.0 / q.cam.r;
         bc[r].atol64 = t.atol64;
         bc[r].atol32 = t.atol32;

@@ -51,6 +51,7 @@ struct DevScene {
     double r_sky, u_sky;
     double rin, rout, power;
     double urin, urout;       // 1/rin, 1/rout: the disk test runs on u = 1/r
+    double uh;                // u at the horizon, 1/(2M) (+inf for M = 0)
     double cell_rad;          // checker cell in radians
     double inv_cell;          // 1 / cell_rad
     const float4* tex;        // sky image (NULL: checker), tex_h rows of tex_w texels
@@ -146,7 +147,7 @@ struct Source {
 // Batched rendering: per-request constants of the integrator (staged in LDS)
 // and of set-up/shading.
 struct BatchConst {
-    double M, usky, urin, urout, u0, atol64;
+    double M, usky, urin, urout, uh, u0, atol64;
     float atol32, pad;
 };
 

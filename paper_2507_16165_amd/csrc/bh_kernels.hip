@@ -440,7 +440,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     const int lane = lane_id();
     // scene constants: wave-uniform for one frame, per lane for a batch
     T M3 = T(3.0 * a.sc.M);
-    double twoM = 2.0 * a.sc.M;
+    double uh = a.sc.uh;
     T usky = T(a.sc.u_sky);
     T urin = T(a.sc.urin), urout = T(a.sc.urout);
     T atol = atol_in;
@@ -472,7 +472,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 if (BATCH) {
                     const BatchConst& c = bct[pf_rq];
                     M3 = T(3.0 * c.M);
-                    twoM = 2.0 * c.M;
+                    uh = c.uh;
                     usky = T(c.usky);
                     urin = T(c.urin);
                     urout = T(c.urout);
@@ -504,7 +504,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             while (cnext >= cend && !drained) {
                 int k = 0;
                 if (lane == 0) k = atomicAdd(&heads[slice * kCtrStride], 1);
-                k = __shfl(k, 0);
+                // lane 0's value, read into a scalar register: the chunk
+                // bounds derived from it stay wave-uniform (scalar ALU)
+                k = __builtin_amdgcn_readlane(k, 0);
                 const int64_t base = ((int64_t)k * nslices + slice) * a.chunk;
                 if (k >= 0 && base < total) {
                     cnext = base;
@@ -563,7 +565,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // Events of an accepted step, in order: disk, horizon, sky sphere.
         const double phin = land ? phik : phx;
         const bool disk_hit = acc && land && un >= urout && un <= urin;
-        const bool capture = acc && !disk_hit && twoM > 0.0 && twoM * (double)un >= 1.0;
+        // Horizon: u >= 1/(2M), the threshold precomputed (no multiply, and
+        // no loop-invariant 2M to hold in a register).
+        const bool capture = acc && !disk_hit && (double)un >= uh;
         const bool skyx = acc && !disk_hit && !capture && un <= usky && wn < T(0);
         const bool advance = acc && !disk_hit && !capture && !skyx;
         // Newton on the step length for u(h) = u_sky, redoing the step from
@@ -604,7 +608,10 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                                 : capture        ? CAPTURED
                                                  : SKY;
             const double pe = sky_done ? phi + (double)hh_new : (capped ? phi : phin);
-            const double rh = disk_hit ? 1.0 / (double)un : 0.0;
+            // r = 1/u: FP32 rays take the hardware reciprocal (1 ulp, far
+            // below their integration error), FP64 rays a correctly rounded
+            // division
+            const double rh = !disk_hit ? 0.0 : sizeof(T) == 4 ? (double)recip(un) : 1.0 / (double)un;
             a.w.res[id] = make_double2(pe, rh);
             a.w.clst[id] = (int32_t)cls | (nsteps << 3);
             active = false;
