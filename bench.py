@@ -4,12 +4,14 @@
 Workload: the 16-frame camera orbit at 3840x2160 (per frame M ~ U[0.5, 2],
 camera at U[20, 100] M, inclination U[0, 90] deg, disk 6-30 M, checker sky at
 1000 M, FOV 60 deg; seeded).  One step = render all 16 frames through the
-whole path (set-up/routing, FP32 integration with the FP64 critical band,
-shading into resident fp32 RGBA buffers).  Value = rays per second of the
-step.  Also reported: the plain FP64 kernel on the same frames; the same
-frames with the surrogate network (trained here on the GPU first); the
-512-request batched-serving mix in one graph-replayed launch; the roofline of
-the dominant kernel (the integrator, timed with HIP events on its launch
+whole path as one batch (set-up/routing of every frame's rays, one
+persistent FP32 integration launch with the FP64 critical band over all of
+them, shading into resident fp32 RGBA buffers).  Value = rays per second of
+the step.  Also reported: the same frames rendered one bh_render call at a
+time; the plain FP64 kernel on the same frames; the same frames with the
+surrogate network (trained here on the GPU first); the 512-request
+batched-serving mix in one graph-replayed launch; the roofline of the
+dominant kernel (the batch integrator, timed with HIP events on its launch
 stream) and of the surrogate's inference kernel; and the CPU FP64 oracle
 timed on a bounded sample.
 
@@ -30,7 +32,11 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_STEP = 139          # algorithmic FLOP per Dormand-Prince step evaluation (FMA = 2)
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (scalar FP32 or FP64 FMA)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_orbit4k_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_batch_orbit4k_traffic.txt")
+ROOFLINE_KERNEL = "bh::k_integrate_fp32_batch"
+# HBM bytes per ray of the batch integrator: start record (16 B) and request
+# index (4 B) read, result record (16 B) and class/step word (4 B) written
+BYTES_PER_RAY = 40
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2507_16165_amd", "csrc", f)
                for f in ("bh_kernels.hip", "bh_internal.h")]
 
@@ -117,22 +123,31 @@ def main() -> int:
     rays_per_step = W * H * len(frames)
     api.reserve(W * H)
     bufs = [torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for _ in frames]
-    opt_fast = api.options(precision=api.FP32)
-    opt_fp64 = api.options(precision=api.FP64)
+    opt_fast = api.options(precision=api.FP32, batch_groups=1)
+    opt_fp64 = api.options(precision=api.FP64, batch_groups=1)
+    batches = {}
 
     def step(opt):
+        """All frames as one batch: one group, three launches."""
+        key = (opt.precision, opt.rtol, opt.rtol_fp32)
+        if key not in batches:
+            batches[key] = api.Batch(frames, opt, use_graph=False, images=bufs)
+        batches[key].launch()
+
+    def step_frames(opt):
+        """The frames one bh_render call each."""
         for f, buf in zip(frames, bufs):
             api.render(f.camera, f.scene, opt, rgba=buf)
 
-    def timed(opt, k, warm):
+    def timed(step_fn, opt, k, warm):
         for _ in range(warm):
-            step(opt)
+            step_fn(opt)
         torch.cuda.synchronize()
         api.timing_enable(True)
         api.timing_read()
         t0 = time.perf_counter()
         for i in range(k):
-            step(opt)
+            step_fn(opt)
             log(f"step {i + 1}/{k} enqueued")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -140,18 +155,25 @@ def main() -> int:
         api.timing_enable(False)
         return (t1 - t0) * 1e3 / k, tim
 
-    log(f"fast path: warmup {args.warmup}, steps {args.steps}")
-    ms_step, tim = timed(opt_fast, args.steps, args.warmup)
+    log(f"fast path (one batch): warmup {args.warmup}, steps {args.steps}")
+    ms_step, tim = timed(step, opt_fast, args.steps, args.warmup)
     log(f"fast path {ms_step:.3f} ms/step")
+    log(f"fast path, one render call per frame: steps {args.steps}")
+    ms_frames, tim_frames = timed(step_frames, opt_fast, args.steps, 1)
+    log(f"per-frame renders {ms_frames:.3f} ms/step")
     if args.fp64_steps > 0:
-        log(f"fp64 path: steps {args.fp64_steps}")
-        ms_step64, tim64 = timed(opt_fp64, args.fp64_steps, 1)
+        log(f"fp64 path (one batch): steps {args.fp64_steps}")
+        ms_step64, tim64 = timed(step, opt_fp64, args.fp64_steps, 1)
         log(f"fp64 path {ms_step64:.3f} ms/step")
     else:
         ms_step64, tim64 = float("nan"), None
+    for b in batches.values():
+        b.close()
+    batches.clear()
 
     # Algorithmic work: step evaluations per ray are independent of the
-    # schedule, so one instrumented pass gives the count of the timed launches.
+    # schedule (the batch's pixels equal the per-frame renders), so one
+    # instrumented per-frame pass gives the count of the timed launches.
     def step_evals(opt):
         tot = 0
         per_path = {}
@@ -162,20 +184,26 @@ def main() -> int:
                 per_path[p] = per_path.get(p, 0) + int((out["path"] == p).sum().item())
         return tot, per_path
 
+    def roof(evals, t, k):
+        """(FLOP per integrator launch, mean launch ms, TFLOP/s) of k timed steps."""
+        ms, n = t["integrate"]
+        flop = evals * FLOP_PER_STEP / (n / k)
+        return flop, ms / n, flop / (ms / n * 1e-3) / 1e12
+
     evals, paths = step_evals(opt_fast)
-    integ_ms, integ_n = tim["integrate"]
-    flop_launch = evals * FLOP_PER_STEP / len(frames)
-    avg_launch_ms = integ_ms / integ_n
-    achieved = flop_launch / (avg_launch_ms * 1e-3) / 1e12
+    flop_launch, avg_launch_ms, achieved = roof(evals, tim, args.steps)
+    _, avg_launch_frames, achieved_frames = roof(evals, tim_frames, args.steps)
     if tim64 is not None:
         evals64, _ = step_evals(opt_fp64)
-        integ_ms64, integ_n64 = tim64["integrate"]
-        achieved64 = (evals64 * FLOP_PER_STEP / len(frames)) / (integ_ms64 / integ_n64 * 1e-3) / 1e12
+        _, _, achieved64 = roof(evals64, tim64, args.fp64_steps)
     else:
         evals64, achieved64 = float("nan"), float("nan")
     traffic = read_traffic()
+    launches_per_step = tim["integrate"][1] // args.steps
+    rays_per_launch = rays_per_step // max(launches_per_step, 1)
 
     value = rays_per_step / (ms_step * 1e-3) / 1e6
+    value_frames = rays_per_step / (ms_frames * 1e-3) / 1e6
     value64 = rays_per_step / (ms_step64 * 1e-3) / 1e6
 
     line = {
@@ -192,11 +220,17 @@ def main() -> int:
         "dtype": "fp32",
         "data": "synthetic",
         "config": {
-            "workload": f"orbit_4k: {len(frames)} frames 3840x2160, disk 6-30 M, checker sky, "
-                        "FP32 integrator + FP64 band |b-3sqrt3 M|<0.05M",
+            "workload": f"orbit_4k: {len(frames)} frames 3840x2160 rendered as one batch, disk 6-30 M, "
+                        "checker sky, FP32 integrator + FP64 band |b-3sqrt3 M|<0.05M",
             "frames": len(frames), "width": W, "height": H, "rays_per_step": rays_per_step,
             "rtol_fp32": opt_fast.rtol_fp32, "rtol_fp64": opt_fast.rtol,
         },
+        "per_frame_renders": {"value": round(value_frames, 2), "unit": "Mrays/s",
+                              "ms_per_step": round(ms_frames, 4),
+                              "integrator_avg_launch_ms": round(avg_launch_frames, 4),
+                              "integrator_tflops": round(achieved_frames, 3),
+                              "kernels_ms_per_step": {k: round(v[0] / args.steps, 4)
+                                                      for k, v in tim_frames.items()}},
         "fp64_plain": {"value": round(value64, 2), "unit": "Mrays/s",
                        "ms_per_step": round(ms_step64, 4), "rtol": opt_fp64.rtol,
                        "achieved_tflops": round(achieved64, 3),
@@ -208,7 +242,7 @@ def main() -> int:
                   "fp32": paths.get(2, 0)},
         "step_evals_per_ray": round(evals / rays_per_step, 3),
         "roofline": {
-            "kernel": "bh::k_integrate_fp32",
+            "kernel": ROOFLINE_KERNEL,
             "bound": "alu",
             "achieved": round(achieved, 3),
             "peak": PEAK_VALU_TFLOPS,
@@ -216,7 +250,8 @@ def main() -> int:
             "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "algorithmic_bytes_per_launch": 36 * W * H,
+            "algorithmic_bytes_per_launch": BYTES_PER_RAY * rays_per_launch,
+            "launches_per_step": launches_per_step,
             "flop_per_launch": flop_launch,
             "avg_launch_ms": round(avg_launch_ms, 4),
         },
@@ -229,7 +264,8 @@ def main() -> int:
         sweep = Sweep(frames[:2], api, torch)
         line["paper_mode_sweep"] = paper_leg(sweep, api)
     if not args.no_surrogate:
-        line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value, step, sweep)
+        line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value_frames, step_frames,
+                                         sweep)
         if sweep is not None:
             line["paper_mode_sweep"]["adaptive_fp32_band_surrogate"] = line["surrogate"].pop("sweep_point")
     
@@ -467,7 +503,7 @@ def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None):
     sur.close()
     res = {
         "value": round(value, 2), "unit": "Mrays/s", "ms_per_step": round(ms, 4),
-        "gain_vs_fp32_band": round(value / value_fast, 4),
+        "gain_vs_fp32_band_per_frame": round(value / value_fast, 4),
         "share": round(n_sur / rays, 4),
         "max_exit_err_rad_vs_fp64": max_err,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},

@@ -281,7 +281,9 @@ bh_status bh_surrogate_trust(const bh_surrogate* s, uint8_t* host_map, int64_t c
 bh_status bh_surrogate_set_trust(bh_surrogate* s, const uint8_t* host_map, int64_t count);
 
 /* Kernel timing for benchmarks.  While enabled, every kernel launch of the
- * library is bracketed by a pair of hipEvents recorded on its launch stream.
+ * library is bracketed by a pair of hipEvents recorded on its launch stream
+ * (batch launches too, each group's set-up, integrator and shading; a batch
+ * replayed from its hipGraph records none).
  * bh_timing_read() waits for those events and returns, per kernel class
  * {0 set-up, 1 integrator, 2 shading, 3 surrogate}, the summed milliseconds
  * and the number of launches since the previous read, then clears them.

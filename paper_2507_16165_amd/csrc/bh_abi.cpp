@@ -472,11 +472,23 @@ struct bh_batch {
 
 namespace {
 // Enqueues a whole batch: start stamp, then each group's sequence.
-hipError_t launch_groups(const bh_batch* b, hipStream_t s) {
+// timed: bracket each launch with the bh_timing events (not while capturing).
+hipError_t launch_groups(const bh_batch* b, hipStream_t s, bool timed) {
     hipError_t e = bh::launch_batch_begin(b->dev, s);
-    for (size_t g = 0; g < b->gdev.size() && e == hipSuccess; ++g)
-        e = bh::launch_batch(b->gdev[g], b->gw[g], b->tol, b->precision, b->cus, b->grid_blocks,
-                             b->chunk, s);
+    for (size_t g = 0; g < b->gdev.size() && e == hipSuccess; ++g) {
+        int t = timed ? timing_begin(0, s) : -1;
+        e = bh::launch_batch_setup(b->gdev[g], b->gw[g], s);
+        timing_end(t, s);
+        if (e != hipSuccess) break;
+        t = timed ? timing_begin(1, s) : -1;
+        e = bh::launch_batch_integrate(b->gdev[g], b->gw[g], b->tol, b->precision, b->cus,
+                                       b->grid_blocks, b->chunk, s);
+        timing_end(t, s);
+        if (e != hipSuccess) break;
+        t = timed ? timing_begin(2, s) : -1;
+        e = bh::launch_batch_shade(b->gdev[g], b->gw[g], b->precision, b->cus, s);
+        timing_end(t, s);
+    }
     return e;
 }
 
@@ -633,7 +645,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
             return cleanup(hip_fail(e, "capture stream"));
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess)
             return cleanup(hip_fail(e, "hipStreamBeginCapture"));
-        e = launch_groups(b, b->cap);
+        e = launch_groups(b, b->cap, false);
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
         b->graph = g;
@@ -654,7 +666,7 @@ bh_status bh_batch_launch(bh_batch* b, void* stream) {
     if (b->use_graph)
         e = hipGraphLaunch(b->exec, s);
     else
-        e = launch_groups(b, s);
+        e = launch_groups(b, s, true);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     b->last = s;
     return BH_OK;

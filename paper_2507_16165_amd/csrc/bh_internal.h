@@ -174,8 +174,12 @@ hipError_t launch_batch_begin(const BatchDev& b, hipStream_t s);
 hipError_t launch_integrate_paper(int64_t n, bool explicit_u0, double u0_uniform,
                                   const DevScene& sc, const DevTol& tol, double eps,
                                   const Work& w, int cus, hipStream_t s);
-hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int precision,
-                        int cus, int grid_blocks, int chunk, hipStream_t s);
+hipError_t launch_batch_setup(const BatchDev& b, const Work& w, hipStream_t s);
+hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol& tol,
+                                  int precision, int cus, int grid_blocks, int chunk,
+                                  hipStream_t s);
+hipError_t launch_batch_shade(const BatchDev& b, const Work& w, int precision, int cus,
+                              hipStream_t s);
 hipError_t launch_reset(int32_t* ctr, hipStream_t s);
 hipError_t launch_setup(const Source& src, const DevScene& sc, const DevRoute& rt, const Work& w,
                         double* out_b, hipStream_t s);

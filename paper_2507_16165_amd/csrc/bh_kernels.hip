@@ -303,20 +303,47 @@ __device__ __forceinline__ void stage_offsets(const BatchDev& b, int64_t* s_off)
     __syncthreads();
 }
 
+// *p, read by every lane from the same address, as wave-uniform values
+// (scalar registers): a request's constants then cost no per-ray loads.
+template <typename S>
+__device__ __forceinline__ S uniform_load(const S* __restrict__ p) {
+    static_assert(sizeof(S) % 4 == 0, "whole dwords");
+    constexpr int n = (int)(sizeof(S) / 4);
+    int v[n];
+    __builtin_memcpy(v, p, sizeof(S));
+#pragma unroll
+    for (int k = 0; k < n; ++k) v[k] = __builtin_amdgcn_readfirstlane(v[k]);
+    S out;
+    __builtin_memcpy(&out, v, sizeof(S));
+    return out;
+}
+
 // Batch set-up: all requests' rays in one index space; each ray also records
-// its request for the integrator.
+// its request for the integrator.  A block whose rays lie in one request (all
+// but a few) takes that request's constants as uniform values; a block that
+// straddles requests looks each ray's request up.
 __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
     extern __shared__ int64_t s_off[];
     stage_offsets(b, s_off);
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t g = g0 + threadIdx.x;
+    const int64_t glast = min(g0 + (int64_t)kBlock, b.total) - 1;
+    const int r0 = __builtin_amdgcn_readfirstlane(find_req(s_off, b.nreq, g0));
     int to = kToNone;
     double bi = 0.0, w0 = 0.0, phi1 = 0.0;
-    if (g < b.total) {
+    if (s_off[r0 + 1] > glast) {
+        const ReqDev q = uniform_load(b.req + r0);
+        if (g < b.total) {
+            w.rq[g] = r0;
+            to = setup_ray(camera_basis(q.cam, g - s_off[r0], q.sc.M, q.sc.r_sky), q.sc, q.rt, g,
+                           w, nullptr, bi, w0, phi1);  // no surrogate routing
+        }
+    } else if (g < b.total) {
         const int r = find_req(s_off, b.nreq, g);
         const ReqDev& q = b.req[r];
         w.rq[g] = r;
         to = setup_ray(camera_basis(q.cam, g - s_off[r], q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
-                       nullptr, bi, w0, phi1);  // no surrogate routing
+                       nullptr, bi, w0, phi1);
     }
     append_band(to == kToBand, g, w0, phi1, w);
 }
@@ -980,36 +1007,38 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
 // finish time (one atomic per chunk and request, so the counters of large
 // requests are not contended).
 constexpr int kShadeChunk = 32 * kBlock;
-static_assert(sizeof(ReqDev) % sizeof(int2) == 0, "ReqDev is copied as int2");
 
 template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
     extern __shared__ int64_t s_off[];
-    __shared__ ReqDev s_q;  // the chunk's request, when the chunk lies in one
     stage_offsets(b, s_off);
     const int64_t nchunks = (b.total + kShadeChunk - 1) / kShadeChunk;
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int64_t c0 = c * kShadeChunk, c1 = min(c0 + kShadeChunk, b.total);
-        const int rc = find_req(s_off, b.nreq, c0);
-        const bool one = s_off[rc + 1] >= c1;  // block-uniform
-        if (one) {
-            const int2* src = reinterpret_cast<const int2*>(b.req + rc);
-            int2* dst = reinterpret_cast<int2*>(&s_q);
-            for (int k = threadIdx.x; k < (int)(sizeof(ReqDev) / sizeof(int2)); k += kBlock)
-                dst[k] = src[k];
-            __syncthreads();
-        }
-        for (int64_t g = c0 + threadIdx.x; g < c1; g += kBlock) {
-            const int r = one ? rc : find_req(s_off, b.nreq, g);
-            const ReqDev& q = one ? s_q : b.req[r];
-            const int64_t i = g - s_off[r];
-            float4* px = reinterpret_cast<float4*>(q.rgba) + i;
-            if (F32) shade_ray32(camera_basis32(q.cam, i), q.sc, w, g, px, Out{}, 0);
-            else shade_ray(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, w, g, px, Out{}, 0);
+        const int rc = __builtin_amdgcn_readfirstlane(find_req(s_off, b.nreq, c0));
+        if (s_off[rc + 1] >= c1) {
+            // the chunk lies in one request: its constants as uniform values
+            const ReqDev q = uniform_load(b.req + rc);
+            const int64_t base = s_off[rc];
+            float4* img = reinterpret_cast<float4*>(q.rgba);
+            for (int64_t g = c0 + threadIdx.x; g < c1; g += kBlock) {
+                const int64_t i = g - base;
+                if (F32) shade_ray32(camera_basis32(q.cam, i), q.sc, w, g, img + i, Out{}, 0);
+                else shade_ray(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, w, g, img + i, Out{}, 0);
+            }
+        } else {
+            for (int64_t g = c0 + threadIdx.x; g < c1; g += kBlock) {
+                const int r = find_req(s_off, b.nreq, g);
+                const ReqDev& q = b.req[r];
+                const int64_t i = g - s_off[r];
+                float4* px = reinterpret_cast<float4*>(q.rgba) + i;
+                if (F32) shade_ray32(camera_basis32(q.cam, i), q.sc, w, g, px, Out{}, 0);
+                else shade_ray(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, w, g, px, Out{}, 0);
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int r = find_req(s_off, b.nreq, c0); r < b.nreq && s_off[r] < c1; ++r) {
+            for (int r = rc; r < b.nreq && s_off[r] < c1; ++r) {
                 const int64_t lo = max(c0, s_off[r]), hi = min(c1, s_off[r + 1]);
                 if (hi <= lo) continue;
                 const unsigned long long cnt = (unsigned long long)(hi - lo);
@@ -1152,15 +1181,19 @@ hipError_t launch_batch_begin(const BatchDev& b, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One group of a batch: b covers the group's requests (offsets relative to
-// the group's first ray) and w its rays.
-hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int precision,
-                        int cus, int grid_blocks, int chunk, hipStream_t s) {
+// One group of a batch, in three launches: b covers the group's requests
+// (offsets relative to the group's first ray) and w its rays.
+hipError_t launch_batch_setup(const BatchDev& b, const Work& w, hipStream_t s) {
     k_reset<<<1, 256, 0, s>>>(w.ctr);
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
     if (b.total > 0) k_setup_batch<<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || b.total == 0) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol& tol,
+                                  int precision, int cus, int grid_blocks, int chunk,
+                                  hipStream_t s) {
+    if (b.total == 0) return hipSuccess;
     IntegArgs a;
     a.n = b.total;
     a.u0 = nullptr;
@@ -1184,8 +1217,13 @@ hipError_t launch_batch(const BatchDev& b, const Work& w, const DevTol& tol, int
         const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
         k_integrate_fp32_batch<<<g, kBlock, lds_c, s>>>(a, band_blocks);
     }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_shade(const BatchDev& b, const Work& w, int precision, int cus,
+                              hipStream_t s) {
+    if (b.total == 0) return hipSuccess;
+    const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
     int64_t gs = (b.total + kShadeChunk - 1) / kShadeChunk;
     if (gs > (int64_t)cus * 8) gs = (int64_t)cus * 8;
     if (precision == 1) k_shade_batch<true><<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
