@@ -442,6 +442,13 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Idle lanes a wavefront waits for before it starts new rays: about the
+// lanes that finish in 2-3 steps (FP32 rays take ~14 step evaluations, FP64
+// rays ~60).  Measured on the 4K orbit: 12 and 6 against 1, 4% and 5% less
+// integrator time.  The FP64 critical band, whose rays are long, refills at
+// once.
+constexpr int kRefill32 = 12, kRefill64 = 6;
+
 // Drains one queue.  VIRTUAL: the queue is the index range [0, total) and
 // the start records come from rec[id] (w0 = NaN: the ray is not for this
 // queue); otherwise queue[] holds ray indices and qrec[] their records.
@@ -463,7 +470,7 @@ template <typename T, bool VIRTUAL, bool BATCH>
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
                           int nslices, T rtol, T atol_in, T ntol,
-                          const BatchConst* __restrict__ bct) {
+                          const BatchConst* __restrict__ bct, int refill_min) {
     const int lane = lane_id();
     // scene constants: wave-uniform for one frame, per lane for a batch
     T M3 = T(3.0 * a.sc.M);
@@ -491,8 +498,12 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     int slice = (int)(blockIdx.x % (unsigned)nslices), dry = 0;
 
     for (;;) {
-        // ---- (A) an idle lane starts its prefetched ray --------------------
-        if (!active && pf_valid) {
+        // ---- (A) idle lanes start their prefetched rays, once at least
+        // refill_min lanes (1..64) are idle or the queue has run dry: the
+        // start and fetch code then runs once for several finished rays
+        // instead of on almost every step --------------------------------------
+        const bool refill = __popcll(__ballot(!active)) >= refill_min || (drained && cnext >= cend);
+        if (refill && !active && pf_valid) {
             pf_valid = false;
             if (!VIRTUAL || pf.x == pf.x) {
                 id = pf_id;
@@ -661,7 +672,7 @@ template <bool BATCH>
 __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     run_queue<double, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
-                                   a.tol.rtol64, a.tol.atol64, a.tol.newton64, bct);
+                                   a.tol.rtol64, a.tol.atol64, a.tol.newton64, bct, kRefill64);
 }
 
 // FP32 mode.  The first `band_blocks` blocks first drain the FP64 queue of
@@ -679,11 +690,11 @@ __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_bloc
         ab.chunk = 64;
         run_queue<double, false, BATCH>(ab, a.w.q64, a.w.q64rec, a.w.ctr[kCtrBandSize],
                                         &a.w.ctr[kCtrBand], 1, a.tol.rtol64, a.tol.atol64,
-                                        a.tol.newton64, bct);
+                                        a.tol.newton64, bct, 1);
         __builtin_amdgcn_s_setprio(0);
     }
     run_queue<float, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
-                                  a.tol.rtol32, a.tol.atol32, a.tol.newton32, bct);
+                                  a.tol.rtol32, a.tol.atol32, a.tol.newton32, bct, kRefill32);
 }
 
 __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
