@@ -405,18 +405,27 @@ __device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T&
     ew = h * fma(e7, g7, fma(e6, g6, fma(e5, g5, fma(e4, g4, fma(e3, g3, e1 * g1)))));
 }
 
-// Step-size factor 0.9 err^(-1/5) without transcendental instructions: an
+// Step-size factor s err^(-1/5) without transcendental instructions: an
 // exponent-field estimate of err^(-1/5) (i_y = 1.2 * bits(1.0f) - bits(err)/5),
 // refined by one Newton step y <- y (6 - err y^5) / 5 (error ~1.5%; the factor
 // is a heuristic, only the accept test needs full precision).  NaN/inf errors
 // give a factor below 0.2, which the callers clamp to 0.2.
+//
+// Safety s: 0.9 for FP64 rays, as the oracle; 0.8 for FP32 rays.  At the
+// FP32 path's tolerances (rtol 1e-6 .. 1e-5) the elementary controller at 0.9
+// keeps proposing steps just too long while the error constant grows towards
+// periapsis (rejected steps had err 1.0-1.5), and about a fifth of all step
+// evaluations were rejections; at 0.8 a ray takes ~15% fewer evaluations with
+// a smaller error.  At FP64 tolerances 0.9 is the cheaper setting.
+template <typename T>
 __device__ __forceinline__ float step_factor(float err) {
+    constexpr float s = sizeof(T) == 4 ? 0.8f : 0.9f;
     err = (err != err) ? 3.0e38f : fmaxf(err, 1e-30f);
     const uint32_t i = __float_as_uint(err);
     const float y = __uint_as_float(1278423859u - i / 5u);
     const float y2 = y * y;
     const float y5 = y2 * y2 * y;
-    return y * fmaf(-err, y5, 6.0f) * (0.9f / 5.0f);
+    return y * fmaf(-err, y5, 6.0f) * (s / 5.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,7 +603,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         const float fsu = (float)su, fsw = (float)sw;
         const float err = fmaxf((float)fabs(eu) * fsw, (float)fabs(ew) * fsu) *
                           __builtin_amdgcn_rcpf(fsu * fsw);
-        const float fac = step_factor(err);
+        const float fac = step_factor<T>(err);
         const float f_acc = fminf(rej ? 1.0f : 5.0f, fmaxf(0.2f, fac));
         const float f_rej = fmaxf(0.2f, fac);
         const bool go = nrm && !capped;               // a trial step was taken
