@@ -82,6 +82,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-row-stride", type=int, default=16)
     ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--rtol-fp32", type=float, default=1e-6,
+                    help="relative tolerance of the FP32 integrator (the library default is 1e-6)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate leg (training and the surrogate render)")
     ap.add_argument("--sur-epochs", type=int, default=40)
@@ -123,7 +125,7 @@ def main() -> int:
     rays_per_step = W * H * len(frames)
     api.reserve(W * H)
     bufs = [torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for _ in frames]
-    opt_fast = api.options(precision=api.FP32, batch_groups=1)
+    opt_fast = api.options(precision=api.FP32, batch_groups=1, rtol_fp32=args.rtol_fp32)
     opt_fp64 = api.options(precision=api.FP64, batch_groups=1)
     batches = {}
 
@@ -258,7 +260,7 @@ def main() -> int:
     }
 
     if not args.no_accuracy:
-        line["accuracy_all_pixels"] = accuracy_leg(frames, api, torch)
+        line["accuracy_all_pixels"] = accuracy_leg(frames, api, torch, opt_fast)
     sweep = None
     if not args.no_paper:
         # the orbit's nearest and farthest camera: the surrogate serves rays
@@ -280,7 +282,7 @@ def main() -> int:
     return 0
 
 
-def accuracy_leg(frames, api, torch):
+def accuracy_leg(frames, api, torch, opt32):
     """Every pixel of the 16 frames: the FP32 + band path against the FP64
     kernel (itself held to the CPU oracle within 1e-8 rad by the parity
     tests).  Rays in the critical band |b - 3 sqrt(3) M| < 0.05 M are the
@@ -290,7 +292,6 @@ def accuracy_leg(frames, api, torch):
     import math
     W, H = frames[0].camera.width, frames[0].camera.height
     fields = ("cls", "b", "exit_dir", "r_hit")
-    opt32 = api.options(precision=api.FP32)
     opt64 = api.options(precision=api.FP64)
     img32 = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
     img64 = torch.empty_like(img32)
@@ -472,7 +473,7 @@ def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None):
                      log=lambda m: log(m) if m.startswith("epoch") and
                      m.split()[1].split("/")[0] in ("1", str(args.sur_epochs)) else None)
     fit_s = time.perf_counter() - t0
-    opt = api.options(precision=api.FP32)
+    opt = api.options(precision=api.FP32, rtol_fp32=args.rtol_fp32)
     opt.surrogate = sur.handle
     for _ in range(args.warmup):
         step(opt)
