@@ -577,10 +577,11 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 cnext += min((int64_t)__popcll(need), avail);
             }
         }
-        if (__ballot(active) == 0) {
-            if (__ballot(pf_valid) == 0 && drained && cnext >= cend) break;
-            continue;
-        }
+        // Done when no lane has a ray or a prefetched one and the queue is
+        // dry.  (A wavefront with no active lane otherwise runs one step with
+        // every lane masked off, at its start and while the queue drains;
+        // the loop keeps a single back edge.)
+        if (__ballot(active || pf_valid) == 0 && drained && cnext >= cend) break;
 
         // ---- (B) one step evaluation per lane ------------------------------
         const bool nrm = active && !refine;           // normal trial step
