@@ -452,11 +452,11 @@ __device__ __forceinline__ double recip(double x) {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Idle lanes a wavefront waits for before it starts new rays: about the
-// lanes that finish in 2-3 steps (FP32 rays take ~14 step evaluations, FP64
-// rays ~60).  Measured on the 4K orbit: 12 and 6 against 1, 4% and 5% less
-// integrator time.  The FP64 critical band, whose rays are long, refills at
-// once.
-constexpr int kRefill32 = 12, kRefill64 = 6;
+// lanes that finish in 3-4 steps (FP32 rays take ~11 step evaluations, FP64
+// rays ~60).  Measured on the 4K orbit: 20 and 6 against 1, about 5% less
+// integrator time each.  The FP64 critical band, whose rays are long, refills
+// at once.
+constexpr int kRefill32 = 20, kRefill64 = 6;
 
 // Drains one queue.  VIRTUAL: the queue is the index range [0, total) and
 // the start records come from rec[id] (w0 = NaN: the ray is not for this
