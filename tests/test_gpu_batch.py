@@ -98,6 +98,40 @@ def test_batch_groups(bh, graph):
     b.close()
 
 
+@pytest.mark.parametrize("groups", [1, 3])
+def test_batch_launches_are_timed(bh, groups):
+    """With bh_timing enabled, an eager batch launch records one set-up, one
+    integrator and one shading launch per group, each with a positive time; a
+    replay of the captured graph records none."""
+    import torch
+    frames = mixed_frames()
+    opt = bh.options(precision=bh.FP32, batch_groups=groups)
+    b = bh.Batch(frames, opt, use_graph=False)
+    bg = bh.Batch(frames, opt, use_graph=True)
+    b.launch()
+    bg.launch()
+    torch.cuda.synchronize()
+    bh.timing_enable(True)
+    try:
+        bh.timing_read()
+        b.launch()
+        torch.cuda.synchronize()
+        t = bh.timing_read()
+        n = t["setup"][1]
+        assert 1 <= n <= groups
+        for k in ("setup", "integrate", "shade"):
+            assert t[k][1] == n and t[k][0] > 0.0, (k, t[k])
+        assert t["surrogate"][1] == 0
+        bg.launch()
+        torch.cuda.synchronize()
+        t = bh.timing_read()
+        assert all(v[1] == 0 for v in t.values()), t
+    finally:
+        bh.timing_enable(False)
+        b.close()
+        bg.close()
+
+
 def test_graph_replays_are_identical(bh):
     """The captured graph replayed several times, with eager work and
     synchronisation in between, reproduces the eager result every time."""
