@@ -603,8 +603,20 @@ def cpu_baseline(frames, stride, bufs, opt_fast, api, torch):
             "kind": "oracle",
             "sample": f"every {stride}th row (offset {stride // 2}) of all {len(frames)} frames: "
                       f"{n} rays, FP64 rtol 1e-10, OpenMP over rows",
-            "seconds": round(secs, 2),
+            "seconds": round(secs, 2), "cpu_model": cpu_model(),
             "gpu_fast_path_max_exit_err_rad_on_sample": max_err}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name, from /proc/cpuinfo ('' where unavailable)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 if __name__ == "__main__":
