@@ -98,6 +98,29 @@ def test_batch_groups(bh, graph):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_orbit4k_batch_equals_per_frame_renders(bh, precision):
+    """The benchmark's launch configuration: the 16 orbit frames at 3840x2160
+    as one batch in one group.  Its pixels equal those of one bh_render call
+    per frame bit for bit (and test_orbit4k_frame_sampled_rows holds those to
+    the oracle at this size)."""
+    import torch
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    frames = inputs.orbit_4k()
+    opt = bh.options(precision=p, batch_groups=1)
+    want = []
+    for f in frames:
+        rgba, _ = bh.render(f.camera, f.scene, opt)
+        want.append(rgba)
+    b = bh.Batch(frames, opt, use_graph=False)
+    b.launch()
+    torch.cuda.synchronize()
+    for k, (img, ref) in enumerate(zip(b.images, want)):
+        assert torch.equal(img, ref), f"frame {k}"
+    assert b.stats()["requests"] == 16
+    b.close()
+
+
 @pytest.mark.parametrize("groups", [1, 3])
 def test_batch_launches_are_timed(bh, groups):
     """With bh_timing enabled, an eager batch launch records one set-up, one
