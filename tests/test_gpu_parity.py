@@ -121,6 +121,22 @@ def test_orbit4k_frame_sampled_rows(bh, ref, k, precision):
     assert np.all(out["cls"] <= 3)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("r_cam,fov,disk", [(400.0, 70.0, (6.0, 300.0)), (3.5, 90.0, (6.0, 20.0)),
+                                            (40.0, 150.0, None)])
+def test_extreme_cameras(bh, ref, precision, r_cam, fov, disk):
+    """Cameras far out (rays reaching the sky sphere with b up to ~340 M, where
+    the FP32 Newton stop leaves its largest residual), just outside the photon
+    sphere, and with a 150-degree field of view: classes, exit directions,
+    disk radii and colours against the oracle."""
+    f = inputs.Frame(inputs.Camera(r_cam, 63.0, 17.0, fov, 72, 40), inputs.scene_in_m(1.0, disk))
+    rgba, out = gpu_render(bh, f, bh.FP64 if precision == "fp64" else bh.FP32)
+    r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
+    s = compare(r_rays, out, f.scene, precision)
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, precision)
+    assert s["n"] == 72 * 40
+
+
 @pytest.mark.parametrize("M,disk", [(1.0, (6.0, 30.0)), (0.5, None), (0.0, (2.0, 40.0))])
 def test_trace_rays_random(bh, ref, M, disk):
     import torch
