@@ -131,3 +131,16 @@ def test_batch_argument_checks():
     assert L.bh_batch_create(reqs, 1, C.byref(o3), 0, C.byref(h)) == api.BH_ERR_UNSUPPORTED
     assert L.bh_batch_launch(None, None) == api.BH_ERR_ARG
     assert L.bh_batch_destroy(None) == api.BH_OK
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py on N > 1 GPUs exits with status 2 and says why, before it
+    touches a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
