@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -45,13 +46,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_of(text: str) -> str:
+    """C/C++ source without comments and with whitespace collapsed: the part
+    of the text that can change the compiled kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash() -> str:
-    """Hash of the integrator's sources (the traffic figure is only valid for
-    the kernel it was counted on)."""
+    """Hash of the integrator's code (comments and layout ignored): the
+    traffic figure is only valid for the kernel it was counted on."""
     h = hashlib.sha256()
     for f in KERNEL_SRCS:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -463,9 +463,10 @@ constexpr int kRefill32 = 20, kRefill64 = 6;
 // queue); otherwise queue[] holds ray indices and qrec[] their records.
 //
 // Each lane keeps the start record of its NEXT ray in registers: the loads
-// are issued one iteration ahead (step C, before the step arithmetic) and
-// consumed when the lane's ray ends (step A).  Positions are handed out per
-// wavefront from a chunk taken with one atomic.
+// are issued at a refill (step C, before the step arithmetic) and consumed
+// when the lane starts that ray (step A, at a later refill, after its current
+// ray has ended).  Positions are handed out per wavefront from a chunk taken
+// with one atomic.
 //
 // The step (B) is a predicated state machine: every lane evaluates one
 // Dormand-Prince step per iteration -- a normal trial step, or a Newton
