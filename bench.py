@@ -31,7 +31,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_STEP = 139          # algorithmic FLOP per Dormand-Prince step evaluation (FMA = 2)
+# Algorithmic FLOP per Dormand-Prince step evaluation (FMA = 2), counted from
+# the kernel's Nystrom-form step: 6 evaluations of g 18, stage sums 35,
+# solution 20, error estimate 22, error scale 4, phi update 1.
+FLOP_PER_STEP = 100
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (scalar FP32 or FP64 FMA)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_batch_orbit4k_traffic.txt")
 ROOFLINE_KERNEL = "bh::k_integrate_fp32_batch"

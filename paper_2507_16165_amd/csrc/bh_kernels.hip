@@ -364,45 +364,58 @@ __device__ __forceinline__ T g_of(T M3, T u) {
 template <typename T>
 __device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T& g7, T& eu,
                                      T& ew) {
-    constexpr T a21 = T(1.0 / 5.0);
-    constexpr T a31 = T(3.0 / 40.0), a32 = T(9.0 / 40.0);
-    constexpr T a41 = T(44.0 / 45.0), a42 = T(-56.0 / 15.0), a43 = T(32.0 / 9.0);
-    constexpr T a51 = T(19372.0 / 6561.0), a52 = T(-25360.0 / 2187.0),
-                a53 = T(64448.0 / 6561.0), a54 = T(-212.0 / 729.0);
-    constexpr T a61 = T(9017.0 / 3168.0), a62 = T(-355.0 / 33.0), a63 = T(46732.0 / 5247.0),
-                a64 = T(49.0 / 176.0), a65 = T(-5103.0 / 18656.0);
-    constexpr T b1 = T(35.0 / 384.0), b3 = T(500.0 / 1113.0), b4 = T(125.0 / 192.0),
-                b5 = T(-2187.0 / 6784.0), b6 = T(11.0 / 84.0);
-    constexpr T e1 = T(71.0 / 57600.0), e3 = T(-71.0 / 16695.0), e4 = T(71.0 / 1920.0),
-                e5 = T(-17253.0 / 339200.0), e6 = T(22.0 / 525.0), e7 = T(-1.0 / 40.0);
+    // The published tableau.
+    constexpr double a21 = 1.0 / 5.0;
+    constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+    constexpr double a41 = 44.0 / 45.0, a42 = -56.0 / 15.0, a43 = 32.0 / 9.0;
+    constexpr double a51 = 19372.0 / 6561.0, a52 = -25360.0 / 2187.0, a53 = 64448.0 / 6561.0,
+                     a54 = -212.0 / 729.0;
+    constexpr double a61 = 9017.0 / 3168.0, a62 = -355.0 / 33.0, a63 = 46732.0 / 5247.0,
+                     a64 = 49.0 / 176.0, a65 = -5103.0 / 18656.0;
+    constexpr double b1 = 35.0 / 384.0, b3 = 500.0 / 1113.0, b4 = 125.0 / 192.0,
+                     b5 = -2187.0 / 6784.0, b6 = 11.0 / 84.0;
+    constexpr double e1 = 71.0 / 57600.0, e3 = -71.0 / 16695.0, e4 = 71.0 / 1920.0,
+                     e5 = -17253.0 / 339200.0, e6 = 22.0 / 525.0, e7 = -1.0 / 40.0;
 
-    const T w1 = w;
-    const T u2 = fma(h, a21 * w1, u);
-    const T w2 = fma(h, a21 * g1, w);
-    const T g2 = g_of(M3, u2);
+    // Nystrom form.  The u component's derivative is w itself, so the w value
+    // of stage j is w + h sum_m a_jm g_m, and the u value of stage k is
+    //   u_k = u + c_k h w + h^2 sum_m abar_km g_m,  c_k = sum_j a_kj,
+    //   abar_km = sum_j a_kj a_jm,
+    // and likewise u_new = u + h w + h^2 sum_m bbar_m g_m with bbar = b A
+    // (sum_j b_j = 1) and the u error h^2 sum_m ebar_m g_m with ebar = e A
+    // (the seventh row of A is b; sum_j e_j = 0).  The same step, without the
+    // five stage sums for w: the products below are evaluated at compile
+    // time from the tableau (bbar_2 = ebar_2 = 0).
+    constexpr double c3 = a31 + a32, c4 = a41 + a42 + a43, c5 = a51 + a52 + a53 + a54;
+    constexpr double A31 = a32 * a21;
+    constexpr double A41 = a42 * a21 + a43 * a31, A42 = a43 * a32;
+    constexpr double A51 = a52 * a21 + a53 * a31 + a54 * a41, A52 = a53 * a32 + a54 * a42,
+                     A53 = a54 * a43;
+    constexpr double A61 = a62 * a21 + a63 * a31 + a64 * a41 + a65 * a51,
+                     A62 = a63 * a32 + a64 * a42 + a65 * a52, A63 = a64 * a43 + a65 * a53,
+                     A64 = a65 * a54;
+    constexpr double B1 = b3 * a31 + b4 * a41 + b5 * a51 + b6 * a61,
+                     B3 = b4 * a43 + b5 * a53 + b6 * a63, B4 = b5 * a54 + b6 * a64,
+                     B5 = b6 * a65;
+    constexpr double E1 = e3 * a31 + e4 * a41 + e5 * a51 + e6 * a61 + e7 * b1,
+                     E3 = e4 * a43 + e5 * a53 + e6 * a63 + e7 * b3,
+                     E4 = e5 * a54 + e6 * a64 + e7 * b4, E5 = e6 * a65 + e7 * b5, E6 = e7 * b6;
 
-    const T u3 = fma(h, fma(a32, w2, a31 * w1), u);
-    const T w3 = fma(h, fma(a32, g2, a31 * g1), w);
-    const T g3 = g_of(M3, u3);
+    const T hw = h * w, h2 = h * h;
+    const T uhw = u + hw;  // c6 = c7 = 1
+    const T g2 = g_of(M3, fma(T(a21), hw, u));
+    const T g3 = g_of(M3, fma(h2, T(A31) * g1, fma(T(c3), hw, u)));
+    const T g4 = g_of(M3, fma(h2, fma(T(A42), g2, T(A41) * g1), fma(T(c4), hw, u)));
+    const T g5 = g_of(M3, fma(h2, fma(T(A53), g3, fma(T(A52), g2, T(A51) * g1)), fma(T(c5), hw, u)));
+    const T g6 =
+        g_of(M3, fma(h2, fma(T(A64), g4, fma(T(A63), g3, fma(T(A62), g2, T(A61) * g1))), uhw));
 
-    const T u4 = fma(h, fma(a43, w3, fma(a42, w2, a41 * w1)), u);
-    const T w4 = fma(h, fma(a43, g3, fma(a42, g2, a41 * g1)), w);
-    const T g4 = g_of(M3, u4);
-
-    const T u5 = fma(h, fma(a54, w4, fma(a53, w3, fma(a52, w2, a51 * w1))), u);
-    const T w5 = fma(h, fma(a54, g4, fma(a53, g3, fma(a52, g2, a51 * g1))), w);
-    const T g5 = g_of(M3, u5);
-
-    const T u6 = fma(h, fma(a65, w5, fma(a64, w4, fma(a63, w3, fma(a62, w2, a61 * w1)))), u);
-    const T w6 = fma(h, fma(a65, g5, fma(a64, g4, fma(a63, g3, fma(a62, g2, a61 * g1)))), w);
-    const T g6 = g_of(M3, u6);
-
-    un = fma(h, fma(b6, w6, fma(b5, w5, fma(b4, w4, fma(b3, w3, b1 * w1)))), u);
-    wn = fma(h, fma(b6, g6, fma(b5, g5, fma(b4, g4, fma(b3, g3, b1 * g1)))), w);
+    un = fma(h2, fma(T(B5), g5, fma(T(B4), g4, fma(T(B3), g3, T(B1) * g1))), uhw);
+    wn = fma(h, fma(T(b6), g6, fma(T(b5), g5, fma(T(b4), g4, fma(T(b3), g3, T(b1) * g1)))), w);
     g7 = g_of(M3, un);
 
-    eu = h * fma(e7, wn, fma(e6, w6, fma(e5, w5, fma(e4, w4, fma(e3, w3, e1 * w1)))));
-    ew = h * fma(e7, g7, fma(e6, g6, fma(e5, g5, fma(e4, g4, fma(e3, g3, e1 * g1)))));
+    eu = h2 * fma(T(E6), g6, fma(T(E5), g5, fma(T(E4), g4, fma(T(E3), g3, T(E1) * g1))));
+    ew = h * fma(T(e7), g7, fma(T(e6), g6, fma(T(e5), g5, fma(T(e4), g4, fma(T(e3), g3, T(e1) * g1)))));
 }
 
 // Step-size factor s err^(-1/5) without transcendental instructions: an
