@@ -76,3 +76,37 @@ def test_forms_agree_on_random_states():
     # scale of its terms
     scale = h * sum(abs(float(E[j])) * np.abs(ws[j]) for j in range(1, 8))
     assert np.max(np.abs(eu2 - eu) / scale) < 1e-13
+
+
+def kernel_constants():
+    """The constexpr coefficients of dp45 in the kernel source, evaluated."""
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = open(os.path.join(root, "paper_2507_16165_amd", "csrc", "bh_kernels.hip")).read()
+    body = src[src.index("void dp45("):]
+    body = body[:body.index("const T hw")]
+    env = {}
+    for stmt in re.findall(r"constexpr double ([^;]+);", body):
+        for part in stmt.split(","):
+            name, expr = (x.strip() for x in part.split("=", 1))
+            assert re.fullmatch(r"[0-9a-zA-Z_.+\-*/ ()]+", expr), expr
+            env[name] = eval(expr, {"__builtins__": {}}, dict(env))  # noqa: S307
+    return env
+
+
+def test_kernel_coefficients_are_the_derived_ones():
+    """The tableau typed into the kernel, and the Nystrom coefficients it
+    derives from it, equal the exact values (to double rounding)."""
+    k = kernel_constants()
+    c, abar, bbar, ebar = derived()
+    want = {f"a{i}{j}": v for (i, j), v in A.items()}
+    want.update({f"b{j}": v for j, v in B.items() if v != 0})
+    want.update({f"e{j}": v for j, v in E.items() if v != 0})
+    want.update({"c3": c[3], "c4": c[4], "c5": c[5]})
+    want.update({f"A{i}{m}": abar[(i, m)] for i in range(3, 7) for m in range(1, i - 1)})
+    want.update({"B1": bbar[1], "B3": bbar[3], "B4": bbar[4], "B5": bbar[5]})
+    want.update({"E1": ebar[1], "E3": ebar[3], "E4": ebar[4], "E5": ebar[5], "E6": ebar[6]})
+    assert set(want) == set(k), sorted(set(want) ^ set(k))
+    for name, v in want.items():
+        assert abs(k[name] - float(v)) <= 4e-16 * max(1.0, abs(float(v))), (name, k[name], float(v))
