@@ -418,11 +418,11 @@ __device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T&
     ew = h * fma(T(e7), g7, fma(T(e6), g6, fma(T(e5), g5, fma(T(e4), g4, fma(T(e3), g3, T(e1) * g1)))));
 }
 
-// Step-size factor s err^(-1/5) without transcendental instructions: an
-// exponent-field estimate of err^(-1/5) (i_y = 1.2 * bits(1.0f) - bits(err)/5),
-// refined by one Newton step y <- y (6 - err y^5) / 5 (error ~1.5%; the factor
-// is a heuristic, only the accept test needs full precision).  NaN/inf errors
-// give a factor below 0.2, which the callers clamp to 0.2.
+// Step-size factor s err^(-1/5) = s 2^(-log2(err) / 5) from the hardware
+// log2 and exp2 (a few ulp; the factor is a heuristic, only the accept test
+// needs full precision).  Their limits give the callers' clamps what they
+// need: err = NaN or inf gives NaN or 0 (clamped to 0.2), err = 0 gives inf
+// (clamped to 5).
 //
 // Safety s: 0.9 for FP64 rays, as the oracle; 0.8 for FP32 rays.  At the
 // FP32 path's tolerances (rtol 1e-6 .. 1e-5) the elementary controller at 0.9
@@ -433,12 +433,7 @@ __device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T&
 template <typename T>
 __device__ __forceinline__ float step_factor(float err) {
     constexpr float s = sizeof(T) == 4 ? 0.8f : 0.9f;
-    err = (err != err) ? 3.0e38f : fmaxf(err, 1e-30f);
-    const uint32_t i = __float_as_uint(err);
-    const float y = __uint_as_float(1278423859u - i / 5u);
-    const float y2 = y * y;
-    const float y5 = y2 * y2 * y;
-    return y * fmaf(-err, y5, 6.0f) * (s / 5.0f);
+    return s * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
 }
 
 // ---------------------------------------------------------------------------
