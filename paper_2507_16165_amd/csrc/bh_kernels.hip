@@ -497,13 +497,16 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     T urin = T(a.sc.urin), urout = T(a.sc.urout);
     T atol = atol_in;
     const T h0 = T(sizeof(T) == 4 ? a.tol.h0_32 : a.tol.h0), hmax = T(a.tol.hmax);
-    const double max_phi = a.tol.max_phi;
+    const T max_phi = T(a.tol.max_phi);
     const int max_steps = a.tol.max_steps;
     int pf_rq = 0;
 
     // ray state
     T u = T(0), w = T(0), g = T(0), h = T(0), hh = T(0);
-    double phi = 0.0, phik = 0.0;
+    // azimuth and the next disk-plane crossing in the ray's precision: FP32
+    // rays are shaded from a float azimuth, so a double one would be rounded
+    // away at the end (about ten float additions per ray, ~1e-6 rad at most)
+    T phi = T(0), phik = T(0);
     int id = 0, attempts = 0, nsteps = 0, it = 0;
     bool rej = false, refine = false, active = false;
     // prefetched next ray
@@ -539,8 +542,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 w = T(pf.x);
                 g = g_of(M3, u);
                 h = h0;
-                phi = 0.0;
-                phik = pf.y;
+                phi = T(0);
+                phik = T(pf.y);
                 attempts = 0;
                 nsteps = 0;
                 it = 0;
@@ -598,9 +601,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         const T hx = refine ? hh : h;
         // A trial step that would pass the next disk-plane crossing is
         // shortened to land on it exactly.
-        const double phx = phi + (double)hx;
+        const T phx = phi + hx;
         const bool land = nrm && phx >= phik;
-        const T ht = land ? T(phik - phi) : hx;
+        const T ht = land ? phik - phi : hx;
         T un, wn, gn, eu, ew;
         dp45<T>(M3, u, w, g, ht, un, wn, gn, eu, ew);
 
@@ -620,7 +623,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         const bool acc = go && fits;
 
         // Events of an accepted step, in order: disk, horizon, sky sphere.
-        const double phin = land ? phik : phx;
+        const T phin = land ? phik : phx;
         const bool disk_hit = acc && land && un >= urout && un <= urin;
         // Horizon: u >= 1/(2M), the threshold precomputed (no multiply, and
         // no loop-invariant 2M to hold in a register).
@@ -645,7 +648,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             rej = !acc;
         }
         if (active && !capped) ++nsteps;
-        if (acc && land && !disk_hit) phik += kPi;
+        if (acc && land && !disk_hit) phik += T(kPi);
         if (advance) {
             u = un;
             w = wn;
@@ -664,7 +667,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                                 : disk_hit       ? DISK
                                 : capture        ? CAPTURED
                                                  : SKY;
-            const double pe = sky_done ? phi + (double)hh_new : (capped ? phi : phin);
+            const double pe = (double)(sky_done ? phi + hh_new : (capped ? phi : phin));
             // r = 1/u: FP32 rays take the hardware reciprocal (1 ulp, far
             // below their integration error), FP64 rays a correctly rounded
             // division
