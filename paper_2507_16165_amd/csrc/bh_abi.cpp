@@ -307,6 +307,17 @@ bh::DevCam make_cam(const bh_camera* cam) {
     c.r0 = sqrt(c.pos[0] * c.pos[0] + c.pos[1] * c.pos[1] + c.pos[2] * c.pos[2]);
     for (int k = 0; k < 3; ++k) c.e1[k] = c.pos[k] / c.r0;
     c.u0 = 1.0 / c.r0;
+    c.inv_w = 1.0 / cam->width;
+    c.hinv_w = 0.5 * c.inv_w;
+    c.wd = cam->width;
+    for (int k = 0; k < 3; ++k) {
+        c.f_right[k] = (float)c.right[k];
+        c.f_up[k] = (float)c.up[k];
+        c.f_e1[k] = (float)c.e1[k];
+    }
+    c.f_ax = (float)c.ax;
+    c.f_bx = (float)c.bx;
+    c.f_tan_half = (float)c.tan_half;
     return c;
 }
 

@@ -77,6 +77,10 @@ struct DevCam {
     double tan_half;          // tan(vfov/2)
     double e1[3], r0, u0;     // C / |C|, |C| (first basis vector of every ray's plane), 1/|C|
     double ax, bx;            // image-plane x of pixel column px: (px + 1/2) ax + bx
+    double inv_w, hinv_w, wd; // 1/W rounded to double, exactly half of it, and W
+    // FP32 copies (rounded once on the host) for the FP32 shading path.
+    float f_right[3], f_up[3], f_e1[3];
+    float f_ax, f_bx, f_tan_half;
     int W, H;
 };
 

@@ -29,7 +29,9 @@ constexpr double kBcrit = 5.19615242270663188058;  // 3 sqrt(3)
 // ---------------------------------------------------------------------------
 struct Basis {
     double e1[3], e2[3];
-    double c, s, is, r0, u0;  // is = 1/s (0 for a radial ray), u0 = 1/r0
+    // p = dv . e1 has the sign of the cosine of the angle between the ray and
+    // e1; p * iv = cos / sin (iv = 1 / |dv - p e1|, 0 for a radial ray).
+    double p, iv, r0, u0;  // u0 = 1/r0
     bool radial, ok;
 };
 
@@ -44,20 +46,21 @@ __device__ __forceinline__ double rsqrt_d(double x) {
     return r;
 }
 
-// Unit direction of pixel i (row-major, row 0 at the top) through the pixel
-// centre; the image-plane coordinates come from per-frame constants.
-__device__ __forceinline__ void camera_dir(const DevCam& cam, int64_t i, double d[3]) {
-    const uint32_t ii = (uint32_t)i, Wu = (uint32_t)cam.W;  // i < 2^31
-    const uint32_t py = ii / Wu, px = ii - py * Wu;
-    const double x = fma((double)px + 0.5, cam.ax, cam.bx);
-    const double y = fma(-((double)py + 0.5), cam.ax, cam.tan_half);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) d[k] = fma(y, cam.up[k], fma(x, cam.right[k], cam.fwd[k]));
+// Column px and row py of pixel i < 2^31 (row-major), as exact doubles.
+// py = trunc((i + 1/2) / W) from one fma with the rounded 1/W: the quotient
+// is within 2^-52 of its true value relative, so within 2^-21 / W, while
+// (i + 1/2) / W lies at least 1/(2W) from every integer; truncation therefore
+// gives floor(i / W) for every W.  px = i - py W is exact (integers < 2^31).
+__device__ __forceinline__ void pixel_of(const DevCam& cam, int64_t i, double& px, double& py) {
+    const double id = (double)(uint32_t)i;
+    py = trunc(fma(id, cam.inv_w, cam.hinv_w));
+    px = fma(-py, cam.wd, id);
 }
 
-// Plane of a ray from r0 e1 with direction dv (any length): c and s are the
-// cosine and sine of the angle between dv and e1, and e2 the unit part of dv
-// orthogonal to e1 (zero for a radial ray).
+// Plane of a ray from r0 e1 with direction dv (any length): v = dv - (dv.e1) e1
+// is the part of dv orthogonal to e1, e2 = v / |v| (zero for a radial ray).
+// Nothing needs dv normalised: the set-up uses the sign of dv.e1 and the
+// ratio cos/sin = (dv.e1) / |v|.
 __device__ __forceinline__ Basis basis_from(const double e1[3], double r0, double u0, bool ok,
                                             const double dv[3], double M, double r_sky) {
     Basis B;
@@ -65,23 +68,18 @@ __device__ __forceinline__ Basis basis_from(const double e1[3], double r0, doubl
     const double dn2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
     B.ok = ok && isfinite(dn2) && (r0 > 3.0 * M) && (r0 < r_sky) && (dn2 > 0.0);
     B.r0 = r0;
-    const double id = B.ok ? rsqrt_d(dn2) : 0.0;
-    double d[3], v[3];
+    double v[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        B.e1[k] = e1[k];
-        d[k] = dv[k] * id;
-    }
-    B.c = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
+    for (int k = 0; k < 3; ++k) B.e1[k] = e1[k];
+    B.p = dv[0] * e1[0] + dv[1] * e1[1] + dv[2] * e1[2];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = d[k] - B.c * e1[k];
+    for (int k = 0; k < 3; ++k) v[k] = dv[k] - B.p * e1[k];
     const double s2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    B.radial = !(s2 > 1e-30);  // sin < 1e-15
-    const double is = B.radial ? 0.0 : rsqrt_d(s2);
-    B.is = is;
-    B.s = s2 * is;
+    B.radial = !(s2 > 1e-30 * dn2);  // sin < 1e-15
+    const double iv = (B.ok && !B.radial) ? rsqrt_d(s2) : 0.0;
+    B.iv = iv;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) B.e2[k] = v[k] * is;
+    for (int k = 0; k < 3; ++k) B.e2[k] = v[k] * iv;
     return B;
 }
 
@@ -93,6 +91,36 @@ __device__ __forceinline__ Basis plane_basis(const double o[3], const double dv[
     const double ir = ok ? rsqrt_d(ro2) : 0.0;
     const double e1[3] = {o[0] * ir, o[1] * ir, o[2] * ir};
     return basis_from(e1, ro2 * ir, ir, ok, dv, M, r_sky);
+}
+
+// Plane of camera pixel i (row 0 at the top, through the pixel centre).  The
+// camera looks at the hole: e1 = C / |C| = -fwd, and right and up are unit
+// vectors orthogonal to fwd and to each other.  The pixel's direction
+// fwd + x right + y up therefore has component -1 along e1 (every camera ray
+// starts inward) and orthogonal part x right + y up, of length
+// sqrt(x^2 + y^2): the plane needs no projection, and has no cancellation
+// near the image centre.
+__device__ __forceinline__ Basis camera_basis(const DevCam& cam, int64_t i, double M,
+                                              double r_sky) {
+    double px, py;
+    pixel_of(cam, i, px, py);
+    const double x = fma(px + 0.5, cam.ax, cam.bx);
+    const double y = fma(-(py + 0.5), cam.ax, cam.tan_half);
+    Basis B;
+    B.u0 = cam.u0;
+    B.r0 = cam.r0;
+    B.ok = (cam.r0 > 3.0 * M) && (cam.r0 < r_sky);
+    B.p = -1.0;
+    const double s2 = fma(x, x, y * y);
+    B.radial = !(s2 > 1e-30);  // sin < 1e-15
+    const double iv = (B.ok && !B.radial) ? rsqrt_d(s2) : 0.0;
+    B.iv = iv;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        B.e1[k] = cam.e1[k];
+        B.e2[k] = fma(x, cam.right[k], y * cam.up[k]) * iv;
+    }
+    return B;
 }
 
 // Plane of ray i of a source (camera pixel, or explicit origin/direction);
@@ -109,15 +137,7 @@ __device__ __forceinline__ Basis source_basis(const Source& src, int64_t i, doub
         }
         return plane_basis(o, dv, M, r_sky);
     }
-    camera_dir(src.cam, i, dv);
-    return basis_from(src.cam.e1, src.cam.r0, src.cam.u0, true, dv, M, r_sky);
-}
-
-__device__ __forceinline__ Basis camera_basis(const DevCam& cam, int64_t i, double M,
-                                              double r_sky) {
-    double dv[3];
-    camera_dir(cam, i, dv);
-    return basis_from(cam.e1, cam.r0, cam.u0, true, dv, M, r_sky);
+    return camera_basis(src.cam, i, M, r_sky);
 }
 
 // First root in (0, pi] of e1z cos(phi) + e2z sin(phi) = 0; +inf if the
@@ -131,12 +151,13 @@ __device__ __forceinline__ double first_crossing(double a, double bz) {
     return p;
 }
 
-// The same root to FP32 accuracy (the FP32 integrator's), a few ulp of atanf.
+// The same root to FP32 accuracy (the FP32 integrator's): the quotient from
+// the hardware reciprocal (1 ulp), then atanf (a few ulp).
 __device__ __forceinline__ double first_crossing32(double a, double bz) {
     if (!(a * a + bz * bz > 1e-30)) return __builtin_inf();
     if (a == 0.0) return kPi;
     if (bz == 0.0) return 0.5 * kPi;
-    double p = (double)atanf(__fdividef((float)-a, (float)bz));
+    double p = (double)atanf(-(float)a * __builtin_amdgcn_rcpf((float)bz));
     if (p <= 0.0) p += kPi;
     return p;
 }
@@ -172,7 +193,7 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
     if (B.ok && B.radial) {
         // Radial ray: inward is captured (flat space: straight through the
         // centre to the antipode); outward escapes along e1.
-        if (B.c < 0.0) {
+        if (B.p < 0.0) {
             cls = sc.M > 0.0 ? CAPTURED : SKY;
             phi_end = sc.M > 0.0 ? 0.0 : kPi;
         } else {
@@ -180,7 +201,7 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
         }
     } else if (B.ok) {
         const double u0 = B.u0;
-        w0 = -u0 * B.c * B.is;
+        w0 = -u0 * B.p * B.iv;
         // First integral of Eq. (1): w^2 + u^2 - 2 M u^3 = 1/b^2.
         const double E0 = w0 * w0 + u0 * u0 - 2.0 * sc.M * u0 * u0 * u0;
         b = rsqrt_d(E0);
@@ -190,12 +211,12 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
         // the disk (u_out^2 - 2 M u_out^3 > 1/b^2: the ray turns before
         // reaching r_out), in a bin the trust map accepts.
         bool sur = false;
-        if (rt.trust && B.c < 0.0 && b > bc + rt.band &&
+        if (rt.trust && B.p < 0.0 && b > bc + rt.band &&
             (!sc.has_disk || sc.urout * sc.urout * (1.0 - 2.0 * sc.M * sc.urout) > E0)) {
             const int bin = trust_bin((float)(b / sc.M), rt.r0m);
             sur = bin >= 0 && rt.trust[bin] != 0;
         }
-        if (rt.analytic_capture && !sc.has_disk && B.c < 0.0 && b < bc - rt.band) {
+        if (rt.analytic_capture && !sc.has_disk && B.p < 0.0 && b < bc - rt.band) {
             cls = CAPTURED;  // below the potential peak: falls in, no disk to hit
         } else if (sur) {
             path = PATH_SUR;
@@ -514,7 +535,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     double2 pf = make_double2(0.0, 0.0);
     double pf_u0 = a.u0_uniform;
     bool pf_valid = false;
-    int64_t cnext = 0, cend = 0;
+    // queue cursor: positions < 2^31 (a render or batch has fewer rays), so
+    // 32-bit wave-uniform values that the scalar unit compares
+    int cnext = 0, cend = 0;
     bool drained = false;
     int slice = (int)(blockIdx.x % (unsigned)nslices), dry = 0;
 
@@ -568,8 +591,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 k = __builtin_amdgcn_readlane(k, 0);
                 const int64_t base = ((int64_t)k * nslices + slice) * a.chunk;
                 if (k >= 0 && base < total) {
-                    cnext = base;
-                    cend = min(base + a.chunk, total);
+                    cnext = (int)base;
+                    cend = (int)min(base + a.chunk, total);
                 } else {
                     slice = slice + 1 == nslices ? 0 : slice + 1;
                     drained = ++dry >= nslices;
@@ -577,23 +600,23 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             }
             if (cnext < cend) {
                 const int rank = rank_in(need);
-                const int64_t avail = cend - cnext;
+                const int avail = cend - cnext;
                 if (!pf_valid && rank < avail) {
-                    const int64_t pos = cnext + rank;
+                    const int pos = cnext + rank;
                     pf_id = VIRTUAL ? (int)pos : queue[pos];
                     pf = VIRTUAL ? a.w.rec[pos] : qrec[pos];
                     if (BATCH) pf_rq = a.w.rq[pf_id];
                     else if (a.u0) pf_u0 = a.u0[pf_id];
                     pf_valid = true;
                 }
-                cnext += min((int64_t)__popcll(need), avail);
+                cnext += min(__popcll(need), avail);
             }
         }
         // Done when no lane has a ray or a prefetched one and the queue is
         // dry.  (A wavefront with no active lane otherwise runs one step with
         // every lane masked off, at its start and while the queue drains;
         // the loop keeps a single back edge.)
-        if (__ballot(active || pf_valid) == 0 && drained && cnext >= cend) break;
+        if (drained && cnext >= cend && __ballot(active || pf_valid) == 0) break;
 
         // ---- (B) one step evaluation per lane ------------------------------
         const bool nrm = active && !refine;           // normal trial step
@@ -831,10 +854,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate_paper(IntegArgs a, double 
 // are mapped and shaded in FP32 (their error budget is 1e-4 rad), the FP64
 // path's in FP64.
 //
-// The FP32 path's mapping back to 3-D, all in FP32: the plane basis from the
-// float camera direction, then the exit vector and the shading.  (A ray
-// whose sin(angle to e1) is s has e2 good to ~1e-7/s; rays with s below
-// ~1e-3 fall in near the axis, where sin(phi_end) is as small.)
+// The FP32 path's mapping back to 3-D, all in FP32: the plane basis, then the
+// exit vector and the shading.  (For an explicit direction the basis is a
+// projection: a ray whose sin(angle to e1) is s has e2 good to ~1e-7/s; rays
+// with s below ~1e-3 fall in near the axis, where sin(phi_end) is as small.)
 struct Basis32 {
     float e1[3], e2[3];
 };
@@ -859,18 +882,22 @@ __device__ __forceinline__ Basis32 basis32(const float e1[3], const float dv[3])
     return B;
 }
 
+// Camera pixel i: the closed form of camera_basis in FP32 (e2 good to a few
+// ulp for every pixel).
 __device__ __forceinline__ Basis32 camera_basis32(const DevCam& cam, int64_t i) {
-    float e1[3], dv[3];
-    const uint32_t ii = (uint32_t)i, Wu = (uint32_t)cam.W;  // i < 2^31
-    const uint32_t py = ii / Wu, px = ii - py * Wu;
-    const float x = fmaf((float)px + 0.5f, (float)cam.ax, (float)cam.bx);
-    const float y = fmaf(-((float)py + 0.5f), (float)cam.ax, (float)cam.tan_half);
+    double px, py;
+    pixel_of(cam, i, px, py);
+    const float x = fmaf((float)px + 0.5f, cam.f_ax, cam.f_bx);
+    const float y = fmaf(-((float)py + 0.5f), cam.f_ax, cam.f_tan_half);
+    const float s2 = fmaf(x, x, y * y);
+    const float iv = s2 > 1e-30f ? __builtin_amdgcn_rsqf(s2) : 0.0f;
+    Basis32 B;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        e1[k] = (float)cam.e1[k];
-        dv[k] = fmaf(y, (float)cam.up[k], fmaf(x, (float)cam.right[k], (float)cam.fwd[k]));
+        B.e1[k] = cam.f_e1[k];
+        B.e2[k] = fmaf(x, cam.f_right[k], y * cam.f_up[k]) * iv;
     }
-    return basis32(e1, dv);
+    return B;
 }
 
 __device__ __forceinline__ Basis32 source_basis32(const Source& src, int64_t i) {
@@ -1257,8 +1284,12 @@ hipError_t launch_batch_shade(const BatchDev& b, const Work& w, int precision, i
                               hipStream_t s) {
     if (b.total == 0) return hipSuccess;
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
+    // One round of resident blocks: a grid beyond them would leave a second,
+    // partly filled round of blocks at the end.
+    const int per_cu = precision == 1 ? blocks_per_cu_lds(k_shade_batch<true>, lds_off)
+                                      : blocks_per_cu_lds(k_shade_batch<false>, lds_off);
     int64_t gs = (b.total + kShadeChunk - 1) / kShadeChunk;
-    if (gs > (int64_t)cus * 8) gs = (int64_t)cus * 8;
+    if (gs > (int64_t)cus * per_cu) gs = (int64_t)cus * per_cu;
     if (precision == 1) k_shade_batch<true><<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
     else k_shade_batch<false><<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
     return hipGetLastError();
