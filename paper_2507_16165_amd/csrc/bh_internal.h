@@ -98,6 +98,9 @@ struct Work {
     double* u0;               // 1/|origin| per ray (explicit-ray mode only)
     double2* rec;             // start record {w0, phi1}; w0 = NaN: not in the main queue
     double2* res;             // result record {phi_end, r_hit}
+    // FP32-mode batches (images only): the result record as {phi_end, r_hit}
+    // in FP32, the FP32 shading's inputs, in res's memory; NULL otherwise
+    float2* res32;
     int32_t* qsur;            // surrogate list (kSurSlices slices): ray indices ...
     double2* qsurrec;         // ... and {b, w0}
     int32_t* rq;              // batch: request index of each ray

@@ -181,6 +181,9 @@ __device__ __forceinline__ double nan_d() { return __builtin_nan(""); }
 // (FP64 band queue), kToSur (surrogate list) or kToNone.
 constexpr int kToNone = 0, kToBand = 1, kToSur = 2;
 
+// R32: the result record of a ray that ends at set-up goes to w.res32 (FP32
+// batches) rather than w.res.
+template <bool R32 = false>
 __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, const DevRoute& rt,
                                          int64_t i, const Work& w, double* out_b, double& b,
                                          double& w0, double& phi1) {
@@ -242,7 +245,8 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
     const bool main = path != PATH_NONE && to == kToNone;
     w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
     if (path == PATH_NONE) {
-        w.res[i] = make_double2(phi_end, 0.0);
+        if (R32) w.res32[i] = make_float2((float)phi_end, 0.0f);
+        else w.res[i] = make_double2(phi_end, 0.0);
         w.clst[i] = cls;
     }
     if (out_b) out_b[i] = b;
@@ -343,6 +347,7 @@ __device__ __forceinline__ S uniform_load(const S* __restrict__ p) {
 // its request for the integrator.  A block whose rays lie in one request (all
 // but a few) takes that request's constants as uniform values; a block that
 // straddles requests looks each ray's request up.
+template <bool R32>
 __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
     extern __shared__ int64_t s_off[];
     stage_offsets(b, s_off);
@@ -356,14 +361,14 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
         const ReqDev q = uniform_load(b.req + r0);
         if (g < b.total) {
             w.rq[g] = r0;
-            to = setup_ray(camera_basis(q.cam, g - s_off[r0], q.sc.M, q.sc.r_sky), q.sc, q.rt, g,
+            to = setup_ray<R32>(camera_basis(q.cam, g - s_off[r0], q.sc.M, q.sc.r_sky), q.sc, q.rt, g,
                            w, nullptr, bi, w0, phi1);  // no surrogate routing
         }
     } else if (g < b.total) {
         const int r = find_req(s_off, b.nreq, g);
         const ReqDev& q = b.req[r];
         w.rq[g] = r;
-        to = setup_ray(camera_basis(q.cam, g - s_off[r], q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
+        to = setup_ray<R32>(camera_basis(q.cam, g - s_off[r], q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
                        nullptr, bi, w0, phi1);
     }
     append_band(to == kToBand, g, w0, phi1, w);
@@ -505,7 +510,8 @@ constexpr int kRefill32 = 20, kRefill64 = 6;
 //
 // BATCH: rays of several requests share the queue; each ray's request index
 // selects its scene constants from a table staged in LDS (`bct`).
-template <typename T, bool VIRTUAL, bool BATCH>
+// R32: result records go to a.w.res32 (FP32 batches).
+template <typename T, bool VIRTUAL, bool BATCH, bool R32>
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
                           int nslices, T rtol, T atol_in, T ntol,
@@ -695,7 +701,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             // below their integration error), FP64 rays a correctly rounded
             // division
             const double rh = !disk_hit ? 0.0 : sizeof(T) == 4 ? (double)recip(un) : 1.0 / (double)un;
-            a.w.res[id] = make_double2(pe, rh);
+            if (R32) a.w.res32[id] = make_float2((float)pe, (float)rh);
+            else a.w.res[id] = make_double2(pe, rh);
             a.w.clst[id] = (int32_t)cls | (nsteps << 3);
             active = false;
         }
@@ -716,11 +723,13 @@ __device__ __forceinline__ const BatchConst* stage_consts(const IntegArgs& a) {
 template <bool BATCH>
 __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
     const BatchConst* bct = stage_consts<BATCH>(a);
-    run_queue<double, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
-                                   a.tol.rtol64, a.tol.atol64, a.tol.newton64, bct, kRefill64);
+    run_queue<double, true, BATCH, false>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
+                                          a.tol.rtol64, a.tol.atol64, a.tol.newton64, bct,
+                                          kRefill64);
 }
 
-// FP32 mode.  The first `band_blocks` blocks first drain the FP64 queue of
+// FP32 mode (batches keep FP32 result records).  The first `band_blocks`
+// blocks first drain the FP64 queue of
 // the critical band, then join the FP32 rays.  Band rays are few but long (up
 // to a few hundred FP64 steps) and latency-bound; their waves start with the
 // launch and run at raised issue priority, so the FP32 waves sharing their
@@ -733,13 +742,14 @@ __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_bloc
         __builtin_amdgcn_s_setprio(3);
         IntegArgs ab = a;
         ab.chunk = 64;
-        run_queue<double, false, BATCH>(ab, a.w.q64, a.w.q64rec, a.w.ctr[kCtrBandSize],
-                                        &a.w.ctr[kCtrBand], 1, a.tol.rtol64, a.tol.atol64,
-                                        a.tol.newton64, bct, 1);
+        run_queue<double, false, BATCH, BATCH>(ab, a.w.q64, a.w.q64rec, a.w.ctr[kCtrBandSize],
+                                               &a.w.ctr[kCtrBand], 1, a.tol.rtol64, a.tol.atol64,
+                                               a.tol.newton64, bct, 1);
         __builtin_amdgcn_s_setprio(0);
     }
-    run_queue<float, true, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
-                                  a.tol.rtol32, a.tol.atol32, a.tol.newton32, bct, kRefill32);
+    run_queue<float, true, BATCH, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
+                                         a.tol.rtol32, a.tol.atol32, a.tol.newton32, bct,
+                                         kRefill32);
 }
 
 __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
@@ -961,10 +971,12 @@ __device__ __forceinline__ float4 sky_texel64(const DevScene& sc, double theta, 
                        lerp2(a.z, b.z, c.z, d.z), lerp2(a.w, b.w, c.w, d.w));
 }
 
+// phi and r_hit come in as floats: the same values whether the record was
+// kept in FP64 (single renders) or FP32 (batches), so both shade alike.
 __device__ __forceinline__ float4 shade_px32(const Basis32& B, const DevScene& sc, uint8_t cls,
-                                             double phi, double r_hit, float sv[3]) {
+                                             float phi, float r_hit, float sv[3]) {
     float sf, cf;
-    sincosf((float)phi, &sf, &cf);
+    sincosf(phi, &sf, &cf);
 #pragma unroll
     for (int k = 0; k < 3; ++k) sv[k] = fmaf(cf, B.e1[k], sf * B.e2[k]);
     if (cls == INVALID) sv[0] = sv[1] = sv[2] = 0.0f;
@@ -982,20 +994,23 @@ __device__ __forceinline__ float4 shade_px32(const Basis32& B, const DevScene& s
             px = make_float4(g, g, g, 1.f);
         }
     } else if (cls == DISK) {
-        const float I = powf((float)(r_hit / sc.rin), (float)sc.power);
+        const float I = powf(r_hit * (float)sc.urin, (float)sc.power);
         px = make_float4(I, 0.6f * I, 0.2f * I, 1.f);
     }
     return px;
 }
 
+// R32: the record is read from w.res32 (FP32 batches).
+template <bool R32 = false>
 __device__ __forceinline__ void shade_ray32(const Basis32& B, const DevScene& sc, const Work& w,
                                             int64_t i, float4* px_out, const Out& out,
                                             int64_t oi) {
     const int32_t cs = w.clst[i];
     const uint8_t cls = (uint8_t)(cs & 7);
-    const double2 rr = w.res[i];
+    const double2 rr = R32 ? make_double2(0.0, 0.0) : w.res[i];
+    const float2 rf = R32 ? w.res32[i] : make_float2((float)rr.x, (float)rr.y);
     float sv[3];
-    const float4 px = shade_px32(B, sc, cls, rr.x, rr.y, sv);
+    const float4 px = shade_px32(B, sc, cls, rf.x, rf.y, sv);
     if (px_out) *px_out = px;
     if (out.cls) out.cls[oi] = cls;
     if (out.phi_end) out.phi_end[oi] = rr.x;
@@ -1083,7 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
             float4* img = reinterpret_cast<float4*>(q.rgba);
             for (int64_t g = c0 + threadIdx.x; g < c1; g += kBlock) {
                 const int64_t i = g - base;
-                if (F32) shade_ray32(camera_basis32(q.cam, i), q.sc, w, g, img + i, Out{}, 0);
+                if (F32) shade_ray32<true>(camera_basis32(q.cam, i), q.sc, w, g, img + i, Out{}, 0);
                 else shade_ray(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, w, g, img + i, Out{}, 0);
             }
         } else {
@@ -1092,7 +1107,7 @@ __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
                 const ReqDev& q = b.req[r];
                 const int64_t i = g - s_off[r];
                 float4* px = reinterpret_cast<float4*>(q.rgba) + i;
-                if (F32) shade_ray32(camera_basis32(q.cam, i), q.sc, w, g, px, Out{}, 0);
+                if (F32) shade_ray32<true>(camera_basis32(q.cam, i), q.sc, w, g, px, Out{}, 0);
                 else shade_ray(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, w, g, px, Out{}, 0);
             }
         }
@@ -1246,7 +1261,10 @@ hipError_t launch_batch_begin(const BatchDev& b, hipStream_t s) {
 hipError_t launch_batch_setup(const BatchDev& b, const Work& w, hipStream_t s) {
     k_reset<<<1, 256, 0, s>>>(w.ctr);
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
-    if (b.total > 0) k_setup_batch<<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
+    if (b.total > 0) {
+        if (w.res32) k_setup_batch<true><<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
+        else k_setup_batch<false><<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
+    }
     return hipGetLastError();
 }
 
@@ -1254,6 +1272,7 @@ hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol
                                   int precision, int cus, int grid_blocks, int chunk,
                                   hipStream_t s) {
     if (b.total == 0) return hipSuccess;
+    if (precision == 1 && !w.res32) return hipErrorInvalidValue;  // FP32 batches: FP32 records
     IntegArgs a;
     a.n = b.total;
     a.u0 = nullptr;
@@ -1283,6 +1302,7 @@ hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol
 hipError_t launch_batch_shade(const BatchDev& b, const Work& w, int precision, int cus,
                               hipStream_t s) {
     if (b.total == 0) return hipSuccess;
+    if (precision == 1 && !w.res32) return hipErrorInvalidValue;  // FP32 batches: FP32 records
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
     // One round of resident blocks: a grid beyond them would leave a second,
     // partly filled round of blocks at the end.
