@@ -611,6 +611,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     b->w.path = (uint8_t*)c; c += sz1;
     b->w.ctr = (int32_t*)c; c += szc;
     b->w.res32 = opt->precision == BH_FP32 ? (float2*)b->w.res : nullptr;
+    b->w.rec32 = opt->precision == BH_FP32 ? (float2*)b->w.rec : nullptr;
     b->w.u0 = nullptr;
     b->w.qsur = nullptr;
     b->w.qsurrec = nullptr;
@@ -651,6 +652,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         wg.rec += base;
         wg.res += base;
         if (wg.res32) wg.res32 += base;
+        if (wg.rec32) wg.rec32 += base;
         wg.clst += base;
         wg.rq += base;
         wg.path += base;

@@ -181,9 +181,10 @@ __device__ __forceinline__ double nan_d() { return __builtin_nan(""); }
 // (FP64 band queue), kToSur (surrogate list) or kToNone.
 constexpr int kToNone = 0, kToBand = 1, kToSur = 2;
 
-// R32: the result record of a ray that ends at set-up goes to w.res32 (FP32
-// batches) rather than w.res.
-template <bool R32 = false>
+// BATCH: no path byte (only single renders report it).  R32 (FP32 batches):
+// the start record goes to w.rec32, and the result record of a ray that ends
+// at set-up to w.res32.
+template <bool BATCH = false, bool R32 = false>
 __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, const DevRoute& rt,
                                          int64_t i, const Work& w, double* out_b, double& b,
                                          double& w0, double& phi1) {
@@ -239,11 +240,12 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
             phi1 = __builtin_inf();
         }
     }
-    w.path[i] = path;
+    if (!BATCH) w.path[i] = path;
     // The main queue is the index range itself; its record marks rays that
     // belong to another path (band, surrogate, set-up only) with w0 = NaN.
     const bool main = path != PATH_NONE && to == kToNone;
-    w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
+    if (R32) w.rec32[i] = make_float2(main ? (float)w0 : __builtin_nanf(""), (float)phi1);
+    else w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
     if (path == PATH_NONE) {
         if (R32) w.res32[i] = make_float2((float)phi_end, 0.0f);
         else w.res[i] = make_double2(phi_end, 0.0);
@@ -361,14 +363,14 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
         const ReqDev q = uniform_load(b.req + r0);
         if (g < b.total) {
             w.rq[g] = r0;
-            to = setup_ray<R32>(camera_basis(q.cam, g - s_off[r0], q.sc.M, q.sc.r_sky), q.sc, q.rt, g,
+            to = setup_ray<true, R32>(camera_basis(q.cam, g - s_off[r0], q.sc.M, q.sc.r_sky), q.sc, q.rt, g,
                            w, nullptr, bi, w0, phi1);  // no surrogate routing
         }
     } else if (g < b.total) {
         const int r = find_req(s_off, b.nreq, g);
         const ReqDev& q = b.req[r];
         w.rq[g] = r;
-        to = setup_ray<R32>(camera_basis(q.cam, g - s_off[r], q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
+        to = setup_ray<true, R32>(camera_basis(q.cam, g - s_off[r], q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
                        nullptr, bi, w0, phi1);
     }
     append_band(to == kToBand, g, w0, phi1, w);
@@ -510,7 +512,8 @@ constexpr int kRefill32 = 20, kRefill64 = 6;
 //
 // BATCH: rays of several requests share the queue; each ray's request index
 // selects its scene constants from a table staged in LDS (`bct`).
-// R32: result records go to a.w.res32 (FP32 batches).
+// R32 (FP32 batches): main-queue start records come from a.w.rec32 and result
+// records go to a.w.res32.
 template <typename T, bool VIRTUAL, bool BATCH, bool R32>
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
@@ -610,7 +613,11 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 if (!pf_valid && rank < avail) {
                     const int pos = cnext + rank;
                     pf_id = VIRTUAL ? (int)pos : queue[pos];
-                    pf = VIRTUAL ? a.w.rec[pos] : qrec[pos];
+                    if (!VIRTUAL) pf = qrec[pos];
+                    else if (R32) {
+                        const float2 r = a.w.rec32[pos];
+                        pf = make_double2(r.x, r.y);
+                    } else pf = a.w.rec[pos];
                     if (BATCH) pf_rq = a.w.rq[pf_id];
                     else if (a.u0) pf_u0 = a.u0[pf_id];
                     pf_valid = true;
@@ -1261,6 +1268,7 @@ hipError_t launch_batch_begin(const BatchDev& b, hipStream_t s) {
 hipError_t launch_batch_setup(const BatchDev& b, const Work& w, hipStream_t s) {
     k_reset<<<1, 256, 0, s>>>(w.ctr);
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
+    if ((w.res32 != nullptr) != (w.rec32 != nullptr)) return hipErrorInvalidValue;
     if (b.total > 0) {
         if (w.res32) k_setup_batch<true><<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
         else k_setup_batch<false><<<blocks_for(b.total), kBlock, lds_off, s>>>(b, w);
@@ -1272,7 +1280,7 @@ hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol
                                   int precision, int cus, int grid_blocks, int chunk,
                                   hipStream_t s) {
     if (b.total == 0) return hipSuccess;
-    if (precision == 1 && !w.res32) return hipErrorInvalidValue;  // FP32 batches: FP32 records
+    if (precision == 1 && (!w.res32 || !w.rec32)) return hipErrorInvalidValue;  // FP32 records
     IntegArgs a;
     a.n = b.total;
     a.u0 = nullptr;
