@@ -464,6 +464,19 @@ __device__ __forceinline__ float step_factor(float err) {
     return s * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
 }
 
+// max(|a|, |b|), and min(a, b) of two non-negative values.  In FP32 as one
+// v_med3 (against FLT_MAX, respectively 0): fmax and fmin in the default IEEE
+// mode also quiet each input not known to be canonical, one more instruction
+// per operand every step, and a med3 against +-inf is folded back into them.
+// (Inputs here are finite, or NaN in a step the error test rejects anyway.)
+// FP64 has no med3.
+__device__ __forceinline__ float max_abs(float a, float b) {
+    return __builtin_amdgcn_fmed3f(fabsf(a), fabsf(b), 3.40282347e38f);
+}
+__device__ __forceinline__ double max_abs(double a, double b) { return fmax(fabs(a), fabs(b)); }
+__device__ __forceinline__ float min2(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double min2(double a, double b) { return fmin(a, b); }
+
 // ---------------------------------------------------------------------------
 // Persistent integrator.
 // ---------------------------------------------------------------------------
@@ -646,8 +659,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // Error test: accept iff |e_i| <= atol + rtol max(|y_i|, |y_new_i|)
         // for both components (exact comparison); the ratio for the step-size
         // proposal needs one reciprocal.
-        const T su = fma(rtol, fmax(fabs(u), fabs(un)), atol);
-        const T sw = fma(rtol, fmax(fabs(w), fabs(wn)), atol);
+        const T su = fma(rtol, max_abs(u, un), atol);
+        const T sw = fma(rtol, max_abs(w, wn), atol);
         const bool fits = fabs(eu) <= su && fabs(ew) <= sw;
         const float fsu = (float)su, fsw = (float)sw;
         const float err = fmaxf((float)fabs(eu) * fsw, (float)fabs(ew) * fsu) *
@@ -680,7 +693,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // State updates.
         if (go) {
             ++attempts;
-            h = fmin(acc ? (land ? h : ht * T(f_acc)) : ht * T(f_rej), hmax);
+            h = min2(acc ? (land ? h : ht * T(f_acc)) : ht * T(f_rej), hmax);
             rej = !acc;
         }
         if (active && !capped) ++nsteps;
