@@ -206,6 +206,8 @@ bh::DevScene dev_scene(const bh_scene* sc) {
     d.urin = sc->has_disk ? 1.0 / sc->disk_rin : 0.0;
     d.urout = sc->has_disk ? 1.0 / sc->disk_rout : 0.0;
     d.uh = sc->M > 0.0 ? 1.0 / (2.0 * sc->M) : INFINITY;
+    d.uh32 = (float)d.uh;
+    if ((double)d.uh32 < d.uh) d.uh32 = nextafterf(d.uh32, INFINITY);
     d.cell_rad = sc->checker_deg * kPi / 180.0;
     d.inv_cell = 1.0 / d.cell_rad;
     d.tex = reinterpret_cast<const float4*>(sc->sky_tex);
@@ -556,10 +558,10 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         bc[r].urin = req[r].sc.urin;
         bc[r].urout = req[r].sc.urout;
         bc[r].uh = req[r].sc.uh;
+        bc[r].uh32 = req[r].sc.uh32;
         bc[r].u0 = 1.0 / q.cam.r;
         bc[r].atol64 = t.atol64;
         bc[r].atol32 = t.atol32;
-        bc[r].pad = 0.0f;
         off[r + 1] = off[r] + (int64_t)q.cam.width * q.cam.height;
     }
     if (off[n] > INT32_MAX) return fail(BH_ERR_ARG, "a batch must have < 2^31 rays");

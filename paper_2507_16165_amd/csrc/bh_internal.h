@@ -52,6 +52,8 @@ struct DevScene {
     double rin, rout, power;
     double urin, urout;       // 1/rin, 1/rout: the disk test runs on u = 1/r
     double uh;                // u at the horizon, 1/(2M) (+inf for M = 0)
+    float uh32;               // the smallest float >= uh: for a float u, u >= uh32
+                              // exactly when (double)u >= uh
     double cell_rad;          // checker cell in radians
     double inv_cell;          // 1 / cell_rad
     const float4* tex;        // sky image (NULL: checker), tex_h rows of tex_w texels
@@ -158,7 +160,7 @@ struct Source {
 // and of set-up/shading.
 struct BatchConst {
     double M, usky, urin, urout, uh, u0, atol64;
-    float atol32, pad;
+    float atol32, uh32;
 };
 
 struct ReqDev {

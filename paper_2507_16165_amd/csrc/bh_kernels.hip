@@ -460,8 +460,9 @@ __device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T&
 // a smaller error.  At FP64 tolerances 0.9 is the cheaper setting.
 template <typename T>
 __device__ __forceinline__ float step_factor(float err) {
-    constexpr float s = sizeof(T) == 4 ? 0.8f : 0.9f;
-    return s * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(err));
+    // s err^(-1/5) = exp2(log2(s) - log2(err) / 5), s = 0.8 (FP32 rays) or 0.9
+    constexpr float log2s = sizeof(T) == 4 ? -0.321928095f : -0.152003093f;
+    return __builtin_amdgcn_exp2f(fmaf(-0.2f, __builtin_amdgcn_logf(err), log2s));
 }
 
 // max(|a|, |b|), and min(a, b) of two non-negative values.  In FP32 as one
@@ -535,7 +536,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     const int lane = lane_id();
     // scene constants: wave-uniform for one frame, per lane for a batch
     T M3 = T(3.0 * a.sc.M);
-    double uh = a.sc.uh;
+    // horizon threshold in the ray's precision: for a float u, u >= uh32
+    // exactly when (double)u >= 1/(2M)
+    T uh = sizeof(T) == 4 ? T(a.sc.uh32) : T(a.sc.uh);
     T usky = T(a.sc.u_sky);
     T urin = T(a.sc.urin), urout = T(a.sc.urout);
     T atol = atol_in;
@@ -576,7 +579,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 if (BATCH) {
                     const BatchConst& c = bct[pf_rq];
                     M3 = T(3.0 * c.M);
-                    uh = c.uh;
+                    uh = sizeof(T) == 4 ? T(c.uh32) : T(c.uh);
                     usky = T(c.usky);
                     urin = T(c.urin);
                     urout = T(c.urout);
@@ -666,17 +669,22 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         const float err = fmaxf((float)fabs(eu) * fsw, (float)fabs(ew) * fsu) *
                           __builtin_amdgcn_rcpf(fsu * fsw);
         const float fac = step_factor<T>(err);
-        const float f_acc = fminf(rej ? 1.0f : 5.0f, fmaxf(0.2f, fac));
-        const float f_rej = fmaxf(0.2f, fac);
         const bool go = nrm && !capped;               // a trial step was taken
         const bool acc = go && fits;
+        // Factor of the next trial step: fac clamped to [0.2, 5] after an
+        // accepted step ([0.2, 1] right after a rejection) and to [0.2, inf)
+        // after a rejected one, as one med3 with its upper bound selected (a
+        // NaN fac, from a step the error test rejected, gives 0.2).
+        const float fcap = acc ? (rej ? 1.0f : 5.0f) : __builtin_inff();
+        const float f = __builtin_amdgcn_fmed3f(fac, 0.2f, fcap);
 
         // Events of an accepted step, in order: disk, horizon, sky sphere.
         const T phin = land ? phik : phx;
         const bool disk_hit = acc && land && un >= urout && un <= urin;
         // Horizon: u >= 1/(2M), the threshold precomputed (no multiply, and
-        // no loop-invariant 2M to hold in a register).
-        const bool capture = acc && !disk_hit && (double)un >= uh;
+        // no loop-invariant 2M to hold in a register); FP32 rays compare with
+        // the smallest float at or above it, which decides as FP64 would.
+        const bool capture = acc && !disk_hit && un >= uh;
         const bool skyx = acc && !disk_hit && !capture && un <= usky && wn < T(0);
         const bool advance = acc && !disk_hit && !capture && !skyx;
         // Newton on the step length for u(h) = u_sky, redoing the step from
@@ -693,7 +701,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // State updates.
         if (go) {
             ++attempts;
-            h = min2(acc ? (land ? h : ht * T(f_acc)) : ht * T(f_rej), hmax);
+            h = min2((acc && land) ? h : ht * T(f), hmax);
             rej = !acc;
         }
         if (active && !capped) ++nsteps;
