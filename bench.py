@@ -38,9 +38,10 @@ FLOP_PER_STEP = 100
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (scalar FP32 or FP64 FMA)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_batch_orbit4k_traffic.txt")
 ROOFLINE_KERNEL = "bh::k_integrate_fp32_batch"
-# HBM bytes per ray of the batch integrator: start record (16 B) and request
-# index (4 B) read, result record (16 B) and class/step word (4 B) written
-BYTES_PER_RAY = 40
+# HBM bytes per ray of the batch integrator (FP32 batches keep FP32 records):
+# start record (8 B) and request index (4 B) read, result record (8 B) and
+# class/step word (4 B) written
+BYTES_PER_RAY = 24
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2507_16165_amd", "csrc", f)
                for f in ("bh_kernels.hip", "bh_internal.h")]
 
