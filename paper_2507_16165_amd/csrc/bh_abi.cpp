@@ -562,6 +562,12 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         bc[r].u0 = 1.0 / q.cam.r;
         bc[r].atol64 = t.atol64;
         bc[r].atol32 = t.atol32;
+        bc[r].M3f = (float)(3.0 * bc[r].M);
+        bc[r].uskyf = (float)bc[r].usky;
+        bc[r].urinf = (float)bc[r].urin;
+        bc[r].uroutf = (float)bc[r].urout;
+        bc[r].u0f = (float)bc[r].u0;
+        bc[r].pad = 0.0f;
         off[r + 1] = off[r] + (int64_t)q.cam.width * q.cam.height;
     }
     if (off[n] > INT32_MAX) return fail(BH_ERR_ARG, "a batch must have < 2^31 rays");

@@ -161,6 +161,9 @@ struct Source {
 struct BatchConst {
     double M, usky, urin, urout, uh, u0, atol64;
     float atol32, uh32;
+    // the FP32 rays' values, rounded once on the host: 3M, u_sky, 1/r_in,
+    // 1/r_out, u0
+    float M3f, uskyf, urinf, uroutf, u0f, pad;
 };
 
 struct ReqDev {

@@ -524,6 +524,9 @@ constexpr int kRefill32 = 20, kRefill64 = 6;
 // landing, horizon, sky crossing, caps) are applied with selects, so the
 // wavefront stays converged except for the store of a finished ray.
 //
+template <bool C, typename A, typename B> struct Pick { using type = A; };
+template <typename A, typename B> struct Pick<false, A, B> { using type = B; };
+
 // BATCH: rays of several requests share the queue; each ray's request index
 // selects its scene constants from a table staged in LDS (`bct`).
 // R32 (FP32 batches): main-queue start records come from a.w.rec32 and result
@@ -557,8 +560,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     bool rej = false, refine = false, active = false;
     // prefetched next ray
     int pf_id = 0;
-    double2 pf = make_double2(0.0, 0.0);
-    double pf_u0 = a.u0_uniform;
+    // (the main queue of an FP32 batch has FP32 start records)
+    typename Pick<R32 && VIRTUAL, float2, double2>::type pf{};
+    T pf_u0 = T(a.u0_uniform);
     bool pf_valid = false;
     // queue cursor: positions < 2^31 (a render or batch has fewer rays), so
     // 32-bit wave-uniform values that the scalar unit compares
@@ -578,13 +582,23 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 id = pf_id;
                 if (BATCH) {
                     const BatchConst& c = bct[pf_rq];
-                    M3 = T(3.0 * c.M);
-                    uh = sizeof(T) == 4 ? T(c.uh32) : T(c.uh);
-                    usky = T(c.usky);
-                    urin = T(c.urin);
-                    urout = T(c.urout);
-                    atol = sizeof(T) == 8 ? T(c.atol64) : T(c.atol32);
-                    pf_u0 = c.u0;
+                    if constexpr (sizeof(T) == 4) {
+                        M3 = c.M3f;
+                        uh = c.uh32;
+                        usky = c.uskyf;
+                        urin = c.urinf;
+                        urout = c.uroutf;
+                        atol = c.atol32;
+                        pf_u0 = c.u0f;
+                    } else {
+                        M3 = 3.0 * c.M;
+                        uh = c.uh;
+                        usky = c.usky;
+                        urin = c.urin;
+                        urout = c.urout;
+                        atol = c.atol64;
+                        pf_u0 = c.u0;
+                    }
                 }
                 u = T(pf_u0);
                 w = T(pf.x);
@@ -629,16 +643,14 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 if (!pf_valid && rank < avail) {
                     const int pos = cnext + rank;
                     pf_id = VIRTUAL ? (int)pos : queue[pos];
-                    if (!VIRTUAL) pf = qrec[pos];
-                    else if (R32) {
-                        const float2 r = a.w.rec32[pos];
-                        pf = make_double2(r.x, r.y);
-                    } else pf = a.w.rec[pos];
+                    if constexpr (!VIRTUAL) pf = qrec[pos];
+                    else if constexpr (R32) pf = a.w.rec32[pos];
+                    else pf = a.w.rec[pos];
                     if (BATCH) pf_rq = a.w.rq[pf_id];
-                    else if (a.u0) pf_u0 = a.u0[pf_id];
+                    else if (a.u0) pf_u0 = T(a.u0[pf_id]);
                     pf_valid = true;
                 }
-                cnext += min(__popcll(need), avail);
+                cnext += min((int)__popcll(need), avail);
             }
         }
         // Done when no lane has a ray or a prefetched one and the queue is
