@@ -114,8 +114,9 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(rendering would shard by interleaved image tiles; see the design notes).",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(an image would shard over GPUs by interleaved 16x16 pixel tiles, each GPU "
+              "running the single-GPU path on its tiles).",
               file=sys.stderr)
         return 2
 

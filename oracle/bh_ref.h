@@ -19,8 +19,7 @@
  *     equatorial disk;
  *   - the endpoint is mapped back to 3D and shaded.
  *
- * Readings taken where the paper is silent or garbled (each one is listed in
- * the design notes of the repository):
+ * Readings taken where the paper is silent or garbled:
  *   - Eq. (1) is printed with a minus sign on u; the Binet equation of the
  *     cited textbook, and every limit the method must reproduce (straight
  *     lines at M = 0, the critical impact parameter 3*sqrt(3)*M, weak-field
