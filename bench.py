@@ -93,7 +93,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-row-stride", type=int, default=16)
+    ap.add_argument("--cpu-row-stride", type=int, default=24)
     ap.add_argument("--frames", type=int, default=16)
     ap.add_argument("--rtol-fp32", type=float, default=1e-6,
                     help="relative tolerance of the FP32 integrator (the library default is 1e-6)")
