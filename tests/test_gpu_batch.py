@@ -69,6 +69,40 @@ def test_batch_equals_per_request_renders(bh, precision, graph):
     b.close()
 
 
+def edge_frames():
+    """Requests at the edges of the scene constants: flat space (M = 0: no
+    horizon, an infinite FP32 horizon threshold), a camera at 400 M with a
+    disk out to 300 M, one just outside the photon sphere, a 150-degree field
+    of view, and a frame larger than one shading chunk."""
+    return [
+        inputs.Frame(inputs.Camera(30.0, 90.0, 0.0, 60.0, 48, 32),
+                     inputs.Scene(M=0.0, r_sky=1000.0, disk=(2.0, 12.0)), "flat"),
+        inputs.Frame(inputs.Camera(400.0, 63.0, 17.0, 70.0, 72, 40), inputs.scene_in_m(1.0, (6.0, 300.0)), "far"),
+        inputs.Frame(inputs.Camera(3.5, 63.0, 17.0, 90.0, 72, 40), inputs.scene_in_m(1.0, (6.0, 20.0)), "near"),
+        inputs.Frame(inputs.Camera(40.0, 63.0, 17.0, 150.0, 72, 40), inputs.scene_in_m(1.0, None), "wide"),
+        inputs.Frame(inputs.Camera(25.0, 80.0, 5.0, 60.0, 300, 200), inputs.scene_in_m(2.0, (6.0, 30.0)), "big"),
+    ]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_edge_requests_equal_single_renders(bh, precision, graph):
+    """FP32 batches keep FP32 start and result records; their pixels must
+    still equal single renders bit for bit at the extremes of the scene
+    constants, FP64 batches likewise."""
+    import torch
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    frames = edge_frames()
+    want = _single(bh, frames, p)
+    b = bh.Batch(frames, bh.options(precision=p), use_graph=graph)
+    for _ in range(2):
+        b.launch()
+        torch.cuda.synchronize()
+        for k, (img, ref) in enumerate(zip(b.images, want)):
+            np.testing.assert_array_equal(img.cpu().numpy(), ref, err_msg=f"request {frames[k].name}")
+    b.close()
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_groups(bh, graph):
     """Requests split into up to 3 consecutive groups traced one after another:

@@ -176,12 +176,14 @@ def test_ragged_and_tiny_images(bh, ref, W, H):
     compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, "fp64")
 
 
-def test_flat_space_render(bh, ref):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_flat_space_render(bh, ref, precision):
     f = inputs.Frame(inputs.Camera(30.0, 90.0, 0.0, 60.0, 48, 32),
                      inputs.Scene(M=0.0, r_sky=1000.0, disk=(2.0, 12.0)))
-    rgba, out = gpu_render(bh, f, bh.FP64)
+    rgba, out = gpu_render(bh, f, bh.FP64 if precision == "fp64" else bh.FP32)
     r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
-    compare(r_rays, out, f.scene, "fp64")
+    compare(r_rays, out, f.scene, precision)
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, precision)
     assert not np.any(out["cls"] == bh.CAPTURED)
 
 
