@@ -205,9 +205,6 @@ bh::DevScene dev_scene(const bh_scene* sc) {
     d.power = sc->has_disk ? sc->disk_power : 0.0;
     d.urin = sc->has_disk ? 1.0 / sc->disk_rin : 0.0;
     d.urout = sc->has_disk ? 1.0 / sc->disk_rout : 0.0;
-    d.uh = sc->M > 0.0 ? 1.0 / (2.0 * sc->M) : INFINITY;
-    d.uh32 = (float)d.uh;
-    if ((double)d.uh32 < d.uh) d.uh32 = nextafterf(d.uh32, INFINITY);
     d.cell_rad = sc->checker_deg * kPi / 180.0;
     d.inv_cell = 1.0 / d.cell_rad;
     d.tex = reinterpret_cast<const float4*>(sc->sky_tex);
@@ -542,6 +539,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     std::vector<bh::ReqDev> req(n);
     std::vector<bh::BatchConst> bc(n);
     std::vector<int64_t> off(n + 1, 0);
+    int any_flat = 0;
     for (int r = 0; r < n; ++r) {
         const bh_request& q = reqs[r];
         if ((st = check_scene(&q.scene)) != BH_OK) return fail(st, "request %d: %s", r, bh_last_error());
@@ -553,21 +551,8 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         req[r].rt = dev_route(opt, &q.scene);
         req[r].rgba = q.rgba;
         const bh::DevTol t = dev_tol(opt, &q.scene);
-        bc[r].M = q.scene.M;
-        bc[r].usky = req[r].sc.u_sky;
-        bc[r].urin = req[r].sc.urin;
-        bc[r].urout = req[r].sc.urout;
-        bc[r].uh = req[r].sc.uh;
-        bc[r].uh32 = req[r].sc.uh32;
-        bc[r].u0 = 1.0 / q.cam.r;
-        bc[r].atol64 = t.atol64;
-        bc[r].atol32 = t.atol32;
-        bc[r].M3f = (float)(3.0 * bc[r].M);
-        bc[r].uskyf = (float)bc[r].usky;
-        bc[r].urinf = (float)bc[r].urin;
-        bc[r].uroutf = (float)bc[r].urout;
-        bc[r].u0f = (float)bc[r].u0;
-        bc[r].pad = 0.0f;
+        bc[r] = bh::integ_consts(req[r].sc, t, 1.0 / q.cam.r);
+        any_flat = any_flat || !(q.scene.M > 0.0);
         off[r + 1] = off[r] + (int64_t)q.cam.width * q.cam.height;
     }
     if (off[n] > INT32_MAX) return fail(BH_ERR_ARG, "a batch must have < 2^31 rays");
@@ -644,6 +629,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     d.done = d_done;
     d.stamp = d_stamp;
     d.req_host0 = req[0].sc;
+    d.any_flat = any_flat;
     for (int g = 0, k = 0; g < G; ++g) {
         const int r0 = gr[g], ng = gr[g + 1] - gr[g];
         const int64_t base = off[r0];

@@ -51,9 +51,6 @@ struct DevScene {
     double r_sky, u_sky;
     double rin, rout, power;
     double urin, urout;       // 1/rin, 1/rout: the disk test runs on u = 1/r
-    double uh;                // u at the horizon, 1/(2M) (+inf for M = 0)
-    float uh32;               // the smallest float >= uh: for a float u, u >= uh32
-                              // exactly when (double)u >= uh
     double cell_rad;          // checker cell in radians
     double inv_cell;          // 1 / cell_rad
     const float4* tex;        // sky image (NULL: checker), tex_h rows of tex_w texels
@@ -156,15 +153,39 @@ struct Source {
     DevCam cam;
 };
 
-// Batched rendering: per-request constants of the integrator (staged in LDS)
-// and of set-up/shading.
+// Integrator constants of one frame (a single render) or one request (a
+// batch, staged in LDS).  The integrator follows the scaled variable v = s u
+// (s = 3M, or 1 for M = 0) and w = dv/dphi, with which Eq. (1) reads
+// v'' + v = k v^2 (k = 1, or 0 for M = 0): each evaluation of the right-hand
+// side is then one fma.  Thresholds are in v: the horizon u = 1/(2M) is
+// v = 3/2 exactly.  integ_consts computes them on the host for single renders
+// and batches alike, so both round every constant the same way.
 struct BatchConst {
-    double M, usky, urin, urout, uh, u0, atol64;
-    float atol32, uh32;
-    // the FP32 rays' values, rounded once on the host: 3M, u_sky, 1/r_in,
-    // 1/r_out, u0
-    float M3f, uskyf, urinf, uroutf, u0f, pad;
+    double s, v0, vsky, vrin, vrout, vh, atol64, k;   // FP64 rays
+    float s32, v032, vsky32, vrin32, vrout32, vh32, atol32, k32;  // FP32 rays
 };
+
+inline BatchConst integ_consts(const DevScene& sc, const DevTol& t, double u0) {
+    BatchConst c;
+    const bool flat = !(sc.M > 0.0);
+    c.s = flat ? 1.0 : 3.0 * sc.M;
+    c.k = flat ? 0.0 : 1.0;
+    c.v0 = c.s * u0;
+    c.vsky = c.s * sc.u_sky;
+    c.vrin = c.s * sc.urin;
+    c.vrout = c.s * sc.urout;
+    c.vh = flat ? __builtin_inf() : 1.5;
+    c.atol64 = c.s * t.atol64;
+    c.s32 = (float)c.s;
+    c.k32 = (float)c.k;
+    c.v032 = (float)c.v0;
+    c.vsky32 = (float)c.vsky;
+    c.vrin32 = (float)c.vrin;
+    c.vrout32 = (float)c.vrout;
+    c.vh32 = (float)c.vh;
+    c.atol32 = (float)(c.s * (double)t.atol32);
+    return c;
+}
 
 struct ReqDev {
     DevCam cam;
@@ -182,6 +203,7 @@ struct BatchDev {
     unsigned long long* done;      // pixels shaded per request
     unsigned long long* stamp;     // finish clock per request; stamp[nreq] = start
     DevScene req_host0;            // unused placeholder scene for the integrator args
+    int any_flat;                  // some request has M = 0 (integrator variant with k)
 };
 
 // Launch helpers (defined in bh_kernels.hip).

@@ -377,10 +377,12 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
 }
 
 // ---------------------------------------------------------------------------
-// Dormand-Prince 5(4) step for y = (u, w), y' = (w, g(u)), g(u) = u (3 M u - 1).
-// First-same-as-last: g1 = g(u) comes in, g7 = g(u_new) goes out.  The u
-// component of every stage derivative is the stage's w value, so only g is
-// evaluated (6 evaluations per step).
+// Dormand-Prince 5(4) step for y = (u, w), y' = (w, g(u)): g(u) = u (3 M u - 1)
+// in the variable u = 1/r (the fixed-step mode), g(v) = v (k v - 1) in the
+// integrator's scaled variable v = s u (s = 3M, k = 1; s = 1, k = 0 for
+// M = 0).  First-same-as-last: g1 = g(u) comes in, g7 = g(u_new) goes out.
+// The u component of every stage derivative is the stage's w value, so only
+// g is evaluated (6 evaluations per step).
 // Tableau: Dormand & Prince (1980); Hairer, Norsett & Wanner, Solving ODEs I,
 // Sec. II.5.
 // ---------------------------------------------------------------------------
@@ -389,9 +391,17 @@ __device__ __forceinline__ T g_of(T M3, T u) {
     return u * fma(M3, u, T(-1));
 }
 
-template <typename T>
-__device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T& g7, T& eu,
-                                     T& ew) {
+// g of the scaled variable: v^2 - v, one fma; with KAPPA, v (k v) - v, whose
+// k = 1 gives the same bits and k = 0 (flat space) gives -v exactly.
+template <bool KAPPA, typename T>
+__device__ __forceinline__ T g_scaled(T k, T v) {
+    if constexpr (KAPPA) return fma(v, v * k, -v);
+    else return fma(v, v, -v);
+}
+
+template <typename T, typename G>
+__device__ __forceinline__ void dp45(const G& g_of, T u, T w, T g1, T h, T& un, T& wn, T& g7,
+                                     T& eu, T& ew) {
     // The published tableau.
     constexpr double a21 = 1.0 / 5.0;
     constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
@@ -431,16 +441,16 @@ __device__ __forceinline__ void dp45(T M3, T u, T w, T g1, T h, T& un, T& wn, T&
 
     const T hw = h * w, h2 = h * h;
     const T uhw = u + hw;  // c6 = c7 = 1
-    const T g2 = g_of(M3, fma(T(a21), hw, u));
-    const T g3 = g_of(M3, fma(h2, T(A31) * g1, fma(T(c3), hw, u)));
-    const T g4 = g_of(M3, fma(h2, fma(T(A42), g2, T(A41) * g1), fma(T(c4), hw, u)));
-    const T g5 = g_of(M3, fma(h2, fma(T(A53), g3, fma(T(A52), g2, T(A51) * g1)), fma(T(c5), hw, u)));
+    const T g2 = g_of(fma(T(a21), hw, u));
+    const T g3 = g_of(fma(h2, T(A31) * g1, fma(T(c3), hw, u)));
+    const T g4 = g_of(fma(h2, fma(T(A42), g2, T(A41) * g1), fma(T(c4), hw, u)));
+    const T g5 = g_of(fma(h2, fma(T(A53), g3, fma(T(A52), g2, T(A51) * g1)), fma(T(c5), hw, u)));
     const T g6 =
-        g_of(M3, fma(h2, fma(T(A64), g4, fma(T(A63), g3, fma(T(A62), g2, T(A61) * g1))), uhw));
+        g_of(fma(h2, fma(T(A64), g4, fma(T(A63), g3, fma(T(A62), g2, T(A61) * g1))), uhw));
 
     un = fma(h2, fma(T(B5), g5, fma(T(B4), g4, fma(T(B3), g3, T(B1) * g1))), uhw);
     wn = fma(h, fma(T(b6), g6, fma(T(b5), g5, fma(T(b4), g4, fma(T(b3), g3, T(b1) * g1)))), w);
-    g7 = g_of(M3, un);
+    g7 = g_of(un);
 
     eu = h2 * fma(T(E6), g6, fma(T(E5), g5, fma(T(E4), g4, fma(T(E3), g3, T(E1) * g1))));
     ew = h * fma(T(e7), g7, fma(T(e6), g6, fma(T(e5), g5, fma(T(e4), g4, fma(T(e3), g3, T(e1) * g1)))));
@@ -491,6 +501,7 @@ struct IntegArgs {
     int chunk;
     const BatchConst* bconst; // batch: per-request constants (global), nreq entries
     int nreq;
+    BatchConst fc;            // single render: the frame's integrator constants
 };
 
 // 1/x in FP64 from the hardware reciprocal estimate and one Newton step
@@ -524,34 +535,44 @@ constexpr int kRefill32 = 20, kRefill64 = 6;
 // landing, horizon, sky crossing, caps) are applied with selects, so the
 // wavefront stays converged except for the store of a finished ray.
 //
+// A frame's or request's integrator constants in the ray's precision.
+template <typename T>
+__device__ __forceinline__ void ray_consts(const BatchConst& c, T& s, T& k, T& vh, T& vsky,
+                                           T& vrin, T& vrout, T& atol, T& v0) {
+    if constexpr (sizeof(T) == 4) {
+        s = c.s32, k = c.k32, vh = c.vh32, vsky = c.vsky32;
+        vrin = c.vrin32, vrout = c.vrout32, atol = c.atol32, v0 = c.v032;
+    } else {
+        s = c.s, k = c.k, vh = c.vh, vsky = c.vsky;
+        vrin = c.vrin, vrout = c.vrout, atol = c.atol64, v0 = c.v0;
+    }
+}
+
 template <bool C, typename A, typename B> struct Pick { using type = A; };
 template <typename A, typename B> struct Pick<false, A, B> { using type = B; };
 
-// BATCH: rays of several requests share the queue; each ray's request index
-// selects its scene constants from a table staged in LDS (`bct`).
+// Constants come from a table staged in LDS (`bct`): one entry for a single
+// frame; with BATCH, rays of several requests share the queue and each ray's
+// request index selects its entry.
 // R32 (FP32 batches): main-queue start records come from a.w.rec32 and result
 // records go to a.w.res32.
-template <typename T, bool VIRTUAL, bool BATCH, bool R32>
+template <typename T, bool VIRTUAL, bool BATCH, bool R32, bool KAPPA>
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
-                          int nslices, T rtol, T atol_in, T ntol,
-                          const BatchConst* __restrict__ bct, int refill_min) {
+                          int nslices, T rtol, T ntol, const BatchConst* __restrict__ bct,
+                          int refill_min) {
     const int lane = lane_id();
-    // scene constants: wave-uniform for one frame, per lane for a batch
-    T M3 = T(3.0 * a.sc.M);
-    // horizon threshold in the ray's precision: for a float u, u >= uh32
-    // exactly when (double)u >= 1/(2M)
-    T uh = sizeof(T) == 4 ? T(a.sc.uh32) : T(a.sc.uh);
-    T usky = T(a.sc.u_sky);
-    T urin = T(a.sc.urin), urout = T(a.sc.urout);
-    T atol = atol_in;
+    // constants in the scaled variable v = s u (s = 3M; s = 1, k = 0 for
+    // M = 0): wave-uniform for one frame, per lane for a batch
+    T s, k, vh, vsky, vrin, vrout, atol, pf_v0;
+    ray_consts(bct[0], s, k, vh, vsky, vrin, vrout, atol, pf_v0);
     const T h0 = T(sizeof(T) == 4 ? a.tol.h0_32 : a.tol.h0), hmax = T(a.tol.hmax);
     const T max_phi = T(a.tol.max_phi);
     const int max_steps = a.tol.max_steps;
     int pf_rq = 0;
 
     // ray state
-    T u = T(0), w = T(0), g = T(0), h = T(0), hh = T(0);
+    T v = T(0), w = T(0), g = T(0), h = T(0), hh = T(0);
     // azimuth and the next disk-plane crossing in the ray's precision: FP32
     // rays are shaded from a float azimuth, so a double one would be rounded
     // away at the end (about ten float additions per ray, ~1e-6 rad at most)
@@ -562,7 +583,6 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     int pf_id = 0;
     // (the main queue of an FP32 batch has FP32 start records)
     typename Pick<R32 && VIRTUAL, float2, double2>::type pf{};
-    T pf_u0 = T(a.u0_uniform);
     bool pf_valid = false;
     // queue cursor: positions < 2^31 (a render or batch has fewer rays), so
     // 32-bit wave-uniform values that the scalar unit compares
@@ -580,29 +600,10 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             pf_valid = false;
             if (!VIRTUAL || pf.x == pf.x) {
                 id = pf_id;
-                if (BATCH) {
-                    const BatchConst& c = bct[pf_rq];
-                    if constexpr (sizeof(T) == 4) {
-                        M3 = c.M3f;
-                        uh = c.uh32;
-                        usky = c.uskyf;
-                        urin = c.urinf;
-                        urout = c.uroutf;
-                        atol = c.atol32;
-                        pf_u0 = c.u0f;
-                    } else {
-                        M3 = 3.0 * c.M;
-                        uh = c.uh;
-                        usky = c.usky;
-                        urin = c.urin;
-                        urout = c.urout;
-                        atol = c.atol64;
-                        pf_u0 = c.u0;
-                    }
-                }
-                u = T(pf_u0);
-                w = T(pf.x);
-                g = g_of(M3, u);
+                if (BATCH) ray_consts(bct[pf_rq], s, k, vh, vsky, vrin, vrout, atol, pf_v0);
+                v = pf_v0;
+                w = s * T(pf.x);
+                g = g_scaled<KAPPA>(k, v);
                 h = h0;
                 phi = T(0);
                 phik = T(pf.y);
@@ -647,7 +648,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                     else if constexpr (R32) pf = a.w.rec32[pos];
                     else pf = a.w.rec[pos];
                     if (BATCH) pf_rq = a.w.rq[pf_id];
-                    else if (a.u0) pf_u0 = T(a.u0[pf_id]);
+                    else if (a.u0) pf_v0 = T(bct[0].s * a.u0[pf_id]);
                     pf_valid = true;
                 }
                 cnext += min((int)__popcll(need), avail);
@@ -668,13 +669,13 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         const T phx = phi + hx;
         const bool land = nrm && phx >= phik;
         const T ht = land ? phik - phi : hx;
-        T un, wn, gn, eu, ew;
-        dp45<T>(M3, u, w, g, ht, un, wn, gn, eu, ew);
+        T vn, wn, gn, eu, ew;
+        dp45<T>([k](T x) { return g_scaled<KAPPA>(k, x); }, v, w, g, ht, vn, wn, gn, eu, ew);
 
         // Error test: accept iff |e_i| <= atol + rtol max(|y_i|, |y_new_i|)
         // for both components (exact comparison); the ratio for the step-size
         // proposal needs one reciprocal.
-        const T su = fma(rtol, max_abs(u, un), atol);
+        const T su = fma(rtol, max_abs(v, vn), atol);
         const T sw = fma(rtol, max_abs(w, wn), atol);
         const bool fits = fabs(eu) <= su && fabs(ew) <= sw;
         const float fsu = (float)su, fsw = (float)sw;
@@ -692,19 +693,18 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
 
         // Events of an accepted step, in order: disk, horizon, sky sphere.
         const T phin = land ? phik : phx;
-        const bool disk_hit = acc && land && un >= urout && un <= urin;
-        // Horizon: u >= 1/(2M), the threshold precomputed (no multiply, and
-        // no loop-invariant 2M to hold in a register); FP32 rays compare with
-        // the smallest float at or above it, which decides as FP64 would.
-        const bool capture = acc && !disk_hit && un >= uh;
-        const bool skyx = acc && !disk_hit && !capture && un <= usky && wn < T(0);
+        const bool disk_hit = acc && land && vn >= vrout && vn <= vrin;
+        // Horizon: u >= 1/(2M) is v >= 3/2, exact in either precision (+inf
+        // for M = 0).
+        const bool capture = acc && !disk_hit && vn >= vh;
+        const bool skyx = acc && !disk_hit && !capture && vn <= vsky && wn < T(0);
         const bool advance = acc && !disk_hit && !capture && !skyx;
-        // Newton on the step length for u(h) = u_sky, redoing the step from
-        // the last accepted state: h <- h - (u(h) - u_sky) / u'(h).  The
-        // accepted crossing step gives the first update; each refinement
+        // Newton on the step length for v(h) = v_sky (u = u_sky), redoing the
+        // step from the last accepted state: h <- h - (v(h) - v_sky) / v'(h).
+        // The accepted crossing step gives the first update; each refinement
         // step gives one more (at most four updates).
         const bool newton = (active && refine) || skyx;
-        const T dh = (un - usky) * recip(wn);
+        const T dh = (vn - vsky) * recip(wn);
         const T hh_new = ht - dh;
         const int it_new = refine ? it + 1 : 1;
         const bool sky_done = newton && (fabs(dh) < ntol || it_new >= 4);
@@ -719,7 +719,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         if (active && !capped) ++nsteps;
         if (acc && land && !disk_hit) phik += T(kPi);
         if (advance) {
-            u = un;
+            v = vn;
             w = wn;
             g = gn;
             phi = phin;
@@ -737,10 +737,12 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                                 : capture        ? CAPTURED
                                                  : SKY;
             const double pe = (double)(sky_done ? phi + hh_new : (capped ? phi : phin));
-            // r = 1/u: FP32 rays take the hardware reciprocal (1 ulp, far
+            // r = 1/u = s/v: FP32 rays take the hardware reciprocal (1 ulp, far
             // below their integration error), FP64 rays a correctly rounded
             // division
-            const double rh = !disk_hit ? 0.0 : sizeof(T) == 4 ? (double)recip(un) : 1.0 / (double)un;
+            const double rh = !disk_hit                ? 0.0
+                              : sizeof(T) == 4 ? (double)(s * recip(vn))
+                                               : (double)s / (double)vn;
             if (R32) a.w.res32[id] = make_float2((float)pe, (float)rh);
             else a.w.res[id] = make_double2(pe, rh);
             a.w.clst[id] = (int32_t)cls | (nsteps << 3);
@@ -749,68 +751,81 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     }
 }
 
-// Stages the batch's per-request scene constants in LDS (batch kernels only).
+// Stages the integrator constants in LDS: a batch's per-request table, or a
+// single frame's constants.  The latter are read back from LDS, so the loop
+// holds them in vector registers; taken from the kernel arguments they would
+// sit in scalar registers, which the FP32 loop would then spill.
 template <bool BATCH>
 __device__ __forceinline__ const BatchConst* stage_consts(const IntegArgs& a) {
-    if (!BATCH) return nullptr;
-    extern __shared__ BatchConst s_bc[];
-    for (int k = threadIdx.x; k < a.nreq; k += blockDim.x) s_bc[k] = a.bconst[k];
-    __syncthreads();
-    return s_bc;
+    if constexpr (BATCH) {
+        extern __shared__ BatchConst s_bc[];
+        for (int k = threadIdx.x; k < a.nreq; k += blockDim.x) s_bc[k] = a.bconst[k];
+        __syncthreads();
+        return s_bc;
+    } else {
+        __shared__ BatchConst s_fc;
+        if (threadIdx.x == 0) s_fc = a.fc;
+        __syncthreads();
+        return &s_fc;
+    }
 }
 
-// FP64 mode: one pass over all rays tagged FP64.
-template <bool BATCH>
+// FP64 mode: one pass over all rays tagged FP64.  KAPPA: some ray's scene
+// is flat (M = 0), so g keeps its factor k.
+template <bool BATCH, bool KAPPA>
 __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
     const BatchConst* bct = stage_consts<BATCH>(a);
-    run_queue<double, true, BATCH, false>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
-                                          a.tol.rtol64, a.tol.atol64, a.tol.newton64, bct,
-                                          kRefill64);
+    run_queue<double, true, BATCH, false, KAPPA>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
+                                                 kSlices, a.tol.rtol64, a.tol.newton64, bct,
+                                                 kRefill64);
 }
 
-// FP32 mode (batches keep FP32 result records).  The first `band_blocks`
-// blocks first drain the FP64 queue of
-// the critical band, then join the FP32 rays.  Band rays are few but long (up
-// to a few hundred FP64 steps) and latency-bound; their waves start with the
-// launch and run at raised issue priority, so the FP32 waves sharing their
-// SIMDs fill the gaps and the band ends inside the FP32 work instead of
-// trailing it.
-template <bool BATCH>
+// FP32 mode (batches keep FP32 records).  The first `band_blocks` blocks
+// first drain the FP64 queue of the critical band, then join the FP32 rays.
+// Band rays are few but long (up to a few hundred FP64 steps) and
+// latency-bound; their waves start with the launch and run at raised issue
+// priority, so the FP32 waves sharing their SIMDs fill the gaps and the band
+// ends inside the FP32 work instead of trailing it.
+template <bool BATCH, bool KAPPA>
 __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_blocks) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     if ((int)blockIdx.x < band_blocks) {
         __builtin_amdgcn_s_setprio(3);
         IntegArgs ab = a;
         ab.chunk = 64;
-        run_queue<double, false, BATCH, BATCH>(ab, a.w.q64, a.w.q64rec, a.w.ctr[kCtrBandSize],
-                                               &a.w.ctr[kCtrBand], 1, a.tol.rtol64, a.tol.atol64,
-                                               a.tol.newton64, bct, 1);
+        run_queue<double, false, BATCH, BATCH, KAPPA>(ab, a.w.q64, a.w.q64rec,
+                                                      a.w.ctr[kCtrBandSize], &a.w.ctr[kCtrBand], 1,
+                                                      a.tol.rtol64, a.tol.newton64, bct, 1);
         __builtin_amdgcn_s_setprio(0);
     }
-    run_queue<float, true, BATCH, BATCH>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices,
-                                         a.tol.rtol32, a.tol.atol32, a.tol.newton32, bct,
-                                         kRefill32);
+    run_queue<float, true, BATCH, BATCH, KAPPA>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
+                                                kSlices, a.tol.rtol32, a.tol.newton32, bct,
+                                                kRefill32);
 }
 
+template <bool KAPPA>
 __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
-    integrate_fp64<false>(a);
+    integrate_fp64<false, KAPPA>(a);
 }
 
 // Held to 64 VGPRs (8 waves per SIMD for the FP32 rays); the FP64 band code
 // spills a few registers, which only band waves pay.
+template <bool KAPPA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
 k_integrate_fp32(IntegArgs a, int band_blocks) {
-    integrate_fp32<false>(a, band_blocks);
+    integrate_fp32<false, KAPPA>(a, band_blocks);
 }
 
 // Batch kernels: per-request constants come from LDS.
+template <bool KAPPA>
 __global__ __launch_bounds__(kBlock) void k_integrate_fp64_batch(IntegArgs a) {
-    integrate_fp64<true>(a);
+    integrate_fp64<true, KAPPA>(a);
 }
 
+template <bool KAPPA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
 k_integrate_fp32_batch(IntegArgs a, int band_blocks) {
-    integrate_fp32<true>(a, band_blocks);
+    integrate_fp32<true, KAPPA>(a, band_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -831,6 +846,7 @@ k_integrate_fp32_batch(IntegArgs a, int band_blocks) {
 __global__ __launch_bounds__(kBlock) void k_integrate_paper(IntegArgs a, double eps) {
     const double M = a.sc.M, M3 = 3.0 * a.sc.M, u_sky = a.sc.u_sky;
     const double R = a.sc.r_sky;
+    const auto gu = [M3](double x) { return g_of(M3, x); };
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
          i += (int64_t)gridDim.x * kBlock) {
         const double2 rec = a.w.rec[i];
@@ -849,7 +865,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate_paper(IntegArgs a, double 
             }
             const double h = atan2(eps * u * u, sqrt(fma(u, u, w * w)) - eps * u * w);
             double un, wn, gn, eu, ew;
-            dp45<double>(M3, u, w, g, h, un, wn, gn, eu, ew);
+            dp45<double>(gu, u, w, g, h, un, wn, gn, eu, ew);
             ++steps;
             const double phin = phi + h;
             const double rn = un > 0.0 ? 1.0 / un : 1e300;
@@ -1261,11 +1277,26 @@ static unsigned persistent_grid(int64_t n, int cus, int per_cu, int grid_blocks)
     return (unsigned)(g > 0 ? g : 1);
 }
 
+template <bool KAPPA>
+static void launch_integrate_k(const IntegArgs& a, int precision, int cus, int grid_blocks,
+                               hipStream_t s) {
+    static int occ64 = 0, occ32 = 0;  // per variant
+    if (precision != 1) {
+        const unsigned g = persistent_grid(a.n, cus, blocks_per_cu(k_integrate_fp64<KAPPA>, &occ64),
+                                           grid_blocks);
+        k_integrate_fp64<KAPPA><<<g, kBlock, 0, s>>>(a);
+    } else {
+        const unsigned g = persistent_grid(a.n, cus, blocks_per_cu(k_integrate_fp32<KAPPA>, &occ32),
+                                           grid_blocks);
+        const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
+        k_integrate_fp32<KAPPA><<<g, kBlock, 0, s>>>(a, band_blocks);
+    }
+}
+
 hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, const DevScene& sc,
                             const DevTol& tol, int precision, const Work& w, int cus,
                             int grid_blocks, int chunk, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    static int occ64 = 0, occ32 = 0;
     IntegArgs a;
     a.n = n;
     a.u0 = explicit_u0 ? w.u0 : nullptr;
@@ -1276,16 +1307,9 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
     a.chunk = chunk;
     a.bconst = nullptr;
     a.nreq = 0;
-    if (precision != 1) {
-        const unsigned g =
-            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp64, &occ64), grid_blocks);
-        k_integrate_fp64<<<g, kBlock, 0, s>>>(a);
-    } else {
-        const unsigned g =
-            persistent_grid(n, cus, blocks_per_cu(k_integrate_fp32, &occ32), grid_blocks);
-        const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
-        k_integrate_fp32<<<g, kBlock, 0, s>>>(a, band_blocks);
-    }
+    a.fc = integ_consts(sc, tol, u0_uniform);
+    if (sc.M > 0.0) launch_integrate_k<false>(a, precision, cus, grid_blocks, s);
+    else launch_integrate_k<true>(a, precision, cus, grid_blocks, s);
     return hipGetLastError();
 }
 
@@ -1309,6 +1333,21 @@ hipError_t launch_batch_setup(const BatchDev& b, const Work& w, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <bool KAPPA>
+static void launch_batch_integrate_k(const IntegArgs& a, int64_t total, size_t lds_c,
+                                     int precision, int cus, int grid_blocks, hipStream_t s) {
+    if (precision != 1) {
+        const unsigned g = persistent_grid(
+            total, cus, blocks_per_cu_lds(k_integrate_fp64_batch<KAPPA>, lds_c), grid_blocks);
+        k_integrate_fp64_batch<KAPPA><<<g, kBlock, lds_c, s>>>(a);
+    } else {
+        const unsigned g = persistent_grid(
+            total, cus, blocks_per_cu_lds(k_integrate_fp32_batch<KAPPA>, lds_c), grid_blocks);
+        const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
+        k_integrate_fp32_batch<KAPPA><<<g, kBlock, lds_c, s>>>(a, band_blocks);
+    }
+}
+
 hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol& tol,
                                   int precision, int cus, int grid_blocks, int chunk,
                                   hipStream_t s) {
@@ -1324,19 +1363,10 @@ hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol
     a.chunk = chunk;
     a.bconst = b.bconst;
     a.nreq = b.nreq;
+    a.fc = BatchConst{};  // unused: batch rays take their request's entry
     const size_t lds_c = sizeof(BatchConst) * b.nreq;
-    if (precision != 1) {
-        const unsigned g =
-            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp64_batch, lds_c),
-                            grid_blocks);
-        k_integrate_fp64_batch<<<g, kBlock, lds_c, s>>>(a);
-    } else {
-        const unsigned g =
-            persistent_grid(b.total, cus, blocks_per_cu_lds(k_integrate_fp32_batch, lds_c),
-                            grid_blocks);
-        const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
-        k_integrate_fp32_batch<<<g, kBlock, lds_c, s>>>(a, band_blocks);
-    }
+    if (b.any_flat) launch_batch_integrate_k<true>(a, b.total, lds_c, precision, cus, grid_blocks, s);
+    else launch_batch_integrate_k<false>(a, b.total, lds_c, precision, cus, grid_blocks, s);
     return hipGetLastError();
 }
 
