@@ -32,12 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic FLOP per Dormand-Prince step evaluation (FMA = 2), counted from
-# the kernel's Nystrom-form step: 6 evaluations of g 18, stage sums 35,
-# solution 20, error estimate 22, error scale 4, phi update 1.
-FLOP_PER_STEP = 100
+# the kernel's Nystrom-form step in the scaled variable v = 3M u: 6 evaluations
+# of g(v) = v^2 - v 12, stage sums 35, solution 20, error estimate 22, error
+# scale 4, phi update 1.
+FLOP_PER_STEP = 94
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (scalar FP32 or FP64 FMA)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_batch_orbit4k_traffic.txt")
-ROOFLINE_KERNEL = "bh::k_integrate_fp32_batch"
+ROOFLINE_KERNEL = "bh::k_integrate_fp32_batch<false>"
 # HBM bytes per ray of the batch integrator (FP32 batches keep FP32 records):
 # start record (8 B) and request index (4 B) read, result record (8 B) and
 # class/step word (4 B) written
