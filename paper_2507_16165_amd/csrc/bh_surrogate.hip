@@ -28,6 +28,9 @@
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
 
 namespace bh {
 
@@ -314,6 +317,23 @@ __global__ void k_adam(int n, float* P, const float* G, float* m, float* v, floa
 constexpr int kInferThreads = 256;
 constexpr int kPackBytes = PK_BF16 * 2 + PK_F32 * 4;
 
+// ReLU of accumulator values off..off+7, rounded to bf16.  Rounding keeps
+// the sign, so the ReLU acts on the bf16 bit patterns as a signed 16-bit max
+// with 0: one packed integer max per two values, where fmaxf in the default
+// IEEE mode costs two float instructions per value (it quiets its input
+// first).  A -0 becomes +0; activations are finite.
+__device__ inline bf16x8 relu_bf16(const f32x16& acc, int off) {
+    uint4 r;
+    uint32_t* q = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const f32x2 x = {acc[off + 2 * k], acc[off + 2 * k + 1]};
+        const i16x2 v = __builtin_bit_cast(i16x2, __builtin_convertvector(x, bf16x2));
+        q[k] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, (i16x2)0));
+    }
+    return __builtin_bit_cast(bf16x8, r);
+}
+
 // NT tiles of 32 rays per call: each weight operand read from LDS feeds NT
 // matrix-core instructions (NT = 2 halves the LDS traffic per ray).
 template <int NT>
@@ -350,11 +370,8 @@ __device__ inline void mlp_tiles(const bf16* __restrict__ pk, const float* __res
             for (int t = 0; t < NT; ++t) {
                 f32x16 acc = {};
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x0[t], acc, 0, 0, 0);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    op[t][2 * mt][e] = (bf16)fmaxf(acc[e], 0.0f);
-                    op[t][2 * mt + 1][e] = (bf16)fmaxf(acc[8 + e], 0.0f);
-                }
+                op[t][2 * mt] = relu_bf16(acc, 0);
+                op[t][2 * mt + 1] = relu_bf16(acc, 8);
             }
         }
     }
@@ -373,26 +390,29 @@ __device__ inline void mlp_tiles(const bf16* __restrict__ pk, const float* __res
                 for (int t = 0; t < NT; ++t) acc[t][mt][r] = bv;
             }
         }
+        // Weight operands double-buffered: the read of the next one is in
+        // flight while the current one feeds the matrix cores.
+        bf16x8 w = pw[l];
 #pragma unroll
         for (int kt = 0; kt < 8; ++kt) {
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const bf16x8 w = pw[(mt * 8 + kt) * 64 + l];
+                const int nx = kt * 4 + mt + 1;
+                bf16x8 wn = w;
+                if (nx < 32) wn = pw[((nx & 3) * 8 + (nx >> 2)) * 64 + l];
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
                     acc[t][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, op[t][kt], acc[t][mt],
                                                                         0, 0, 0);
+                w = wn;
             }
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    op[t][2 * mt][e] = (bf16)fmaxf(acc[t][mt][e], 0.0f);
-                    op[t][2 * mt + 1][e] = (bf16)fmaxf(acc[t][mt][8 + e], 0.0f);
-                }
+                op[t][2 * mt] = relu_bf16(acc[t][mt], 0);
+                op[t][2 * mt + 1] = relu_bf16(acc[t][mt], 8);
             }
         }
     }
@@ -531,9 +551,9 @@ __global__ void k_labels_finish(int64_t n, uint8_t* cls_cap, double* phi) {
 
 // ---------------------------------------------------------------------------
 // Render path: the surrogate list that set-up fills (kSlices slices of ray
-// indices with {b, w0}).  Tiles of 32 listed rays are dealt to wavefronts
-// round-robin (every tile costs the same); a wavefront loads its next tile's
-// entries before it evaluates the current one.  The exit azimuth goes straight
+// indices with {b, w0}).  Tiles of 32 listed rays are dealt to wavefronts in
+// pairs, round-robin (every tile costs the same); a wavefront loads its next
+// pair's entries before it evaluates the current one.  The exit azimuth goes straight
 // into the result record.  A ray whose capture logit disagrees with b > b_c is
 // handed back to the FP32 integrator by restoring its start record.
 // ---------------------------------------------------------------------------
@@ -541,17 +561,19 @@ struct SurRender {
     int64_t slice_cap;  // entries per slice of the list
     Work w;
     float r0m;     // camera distance / M
+    float inv_r0m; // M / camera distance
     double inv_M;  // 1/M
 };
 
 // The render path's exit azimuth in FP32 (its error budget is 1e-4 rad):
-// first-order sweep plus the scaled network output.
-__device__ inline float sweep1f(float b, float r0) {
-    auto a = [b](float r) {
-        float x = b / r - (2.0f - b * b / (r * r)) / b;
+// first-order sweep plus the scaled network output.  ib = 1/b (hardware
+// reciprocal, 1 ulp), ir0 = 1/r0; with q = b/r, a(r) = asin(q - (2 - q^2)/b).
+__device__ inline float sweep1f(float b, float ib, float ir0) {
+    auto a = [ib](float q) {
+        const float x = q - (2.0f - q * q) * ib;
         return asinf(fminf(1.0f, fmaxf(-1.0f, x)));
     };
-    return 3.14159265f - a(1000.0f) - a(r0);
+    return 3.14159265f - a(b * (1.0f / 1000.0f)) - a(b * ir0);
 }
 
 __device__ inline void sur_finish(const SurRender& a, int id, double w0, float bm, float y0,
@@ -561,7 +583,8 @@ __device__ inline void sur_finish(const SurRender& a, int id, double w0, float b
         a.w.path[id] = PATH_FP32;
         return;
     }
-    const float phi = sweep1f(bm, a.r0m) + (12.0f / (bm * bm)) * y0;
+    const float ib = __builtin_amdgcn_rcpf(bm);
+    const float phi = sweep1f(bm, ib, a.inv_r0m) + (12.0f * ib * ib) * y0;
     a.w.res[id] = make_double2((double)phi, 0.0);
     a.w.clst[id] = 0;  // SKY, no integration steps
 }
@@ -587,6 +610,10 @@ __device__ inline SurEntry sur_entry(const int* cnt, const int* first, int64_t s
     return {lo * slice_cap + (valid ? j : 0), valid};
 }
 
+// A wavefront evaluates two tiles per pass (tiles 2p and 2p + 1 of pair p):
+// each weight operand read from LDS then feeds two matrix-core instructions.
+// With one tile per pass the four SIMDs of a CU need about 128 B of LDS reads
+// per clock at the matrix-core rate, the whole LDS bandwidth.
 __global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void k_sur_render(const void* __restrict__ pack, SurRender a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -603,40 +630,56 @@ void k_sur_render(const void* __restrict__ pack, SurRender a) {
     }
     __syncthreads();
     const int64_t tiles = s_first[kSurSlices];
+    const int64_t pairs = (tiles + 1) / 2;
     constexpr int wpb = kInferThreads / 64;
-    if ((int64_t)blockIdx.x * wpb >= tiles) return;  // block-uniform: nothing for this block
+    if ((int64_t)blockIdx.x * wpb >= pairs) return;  // block-uniform: nothing for this block
     load_pack(pack, smem);
     const bf16* pk = reinterpret_cast<const bf16*>(smem);
     const float* pkf = reinterpret_cast<const float*>(smem + PK_BF16 * 2);
     const int l = threadIdx.x & 63;
     const float f2v = feature2(a.r0m);
     const int64_t nw = (int64_t)gridDim.x * wpb;
-    int64_t t = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-    SurEntry e{0, false};
-    int id = 0, slice = 0;
-    double2 rec = make_double2(10.0, 0.0);
-    if (t < tiles) {
-        e = sur_entry(s_cnt, s_first, a.slice_cap, t, l & 31, slice);
-        id = a.w.qsur[e.slot];
-        rec = a.w.qsurrec[e.slot];
-    }
-    for (; t < tiles; t += nw) {
-        // next tile's entries in flight while this one is evaluated
-        SurEntry en{0, false};
-        int idn = 0;
-        double2 recn = make_double2(10.0, 0.0);
-        if (t + nw < tiles) {
-            en = sur_entry(s_cnt, s_first, a.slice_cap, t + nw, l & 31, slice);
-            idn = a.w.qsur[en.slot];
-            recn = a.w.qsurrec[en.slot];
+    int64_t p = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    int slice = 0;
+    // Entries of the two tiles of pair q (a tile past the list is not valid).
+    auto fetch = [&](int64_t q, SurEntry (&e)[2], int (&id)[2], double2 (&rec)[2]) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            e[k] = SurEntry{0, false};
+            id[k] = 0;
+            rec[k] = make_double2(10.0, 0.0);
+            const int64_t t = 2 * q + k;
+            if (q < pairs && t < tiles) {
+                e[k] = sur_entry(s_cnt, s_first, a.slice_cap, t, l & 31, slice);
+                id[k] = a.w.qsur[e[k].slot];
+                rec[k] = a.w.qsurrec[e[k].slot];
+            }
         }
-        const float bm = (float)(rec.x * a.inv_M);
-        float f1 = feature1(bm), f2 = f2v, y0, y1;
-        mlp_tiles<1>(pk, pkf, &f1, &f2, &y0, &y1);
-        if (l < 32 && e.valid) sur_finish(a, id, rec.y, bm, y0, y1);
-        e = en;
-        id = idn;
-        rec = recn;
+    };
+    SurEntry e[2];
+    int id[2];
+    double2 rec[2];
+    fetch(p, e, id, rec);
+    for (; p < pairs; p += nw) {
+        // next pair's entries in flight while this one is evaluated
+        SurEntry en[2];
+        int idn[2];
+        double2 recn[2];
+        fetch(p + nw, en, idn, recn);
+        float bm[2], f1[2], f2[2] = {f2v, f2v}, y0[2], y1[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            bm[k] = (float)(rec[k].x * a.inv_M);
+            f1[k] = feature1(bm[k]);
+        }
+        mlp_tiles<2>(pk, pkf, f1, f2, y0, y1);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (l < 32 && e[k].valid) sur_finish(a, id[k], rec[k].y, bm[k], y0[k], y1[k]);
+            e[k] = en[k];
+            id[k] = idn[k];
+            rec[k] = recn[k];
+        }
     }
 }
 
@@ -646,11 +689,12 @@ hipError_t launch_surrogate_render(int64_t n, const Work& w, const void* pack, d
     a.slice_cap = sur_slice_cap(n);
     a.w = w;
     a.r0m = (float)(r_cam / M);
+    a.inv_r0m = (float)(M / r_cam);
     a.inv_M = 1.0 / M;
     // Two blocks per CU (the weights fill ~66 KB of LDS per block); blocks
     // beyond the list's tiles return at once.
     int64_t g = (int64_t)cus * 2;
-    const int64_t need = (n + 32 * (kInferThreads / 64) - 1) / (32 * (kInferThreads / 64));
+    const int64_t need = (n + 64 * (kInferThreads / 64) - 1) / (64 * (kInferThreads / 64));
     if (g > need) g = need > 0 ? need : 1;
     k_sur_render<<<(unsigned)g, kInferThreads, kPackBytes, s>>>(pack, a);
     return hipGetLastError();
