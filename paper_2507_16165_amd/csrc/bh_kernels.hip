@@ -475,18 +475,27 @@ __device__ __forceinline__ float step_factor(float err) {
     return __builtin_amdgcn_exp2f(fmaf(-0.2f, __builtin_amdgcn_logf(err), log2s));
 }
 
-// max(|a|, |b|), and min(a, b) of two non-negative values.  In FP32 as one
-// v_med3 (against FLT_MAX, respectively 0): fmax and fmin in the default IEEE
-// mode also quiet each input not known to be canonical, one more instruction
-// per operand every step, and a med3 against +-inf is folded back into them.
-// (Inputs here are finite, or NaN in a step the error test rejects anyway.)
-// FP64 has no med3.
+// max(|a|, |b|), and min(a, b) of two non-negative values, as one
+// instruction each.  fmax and fmin in the default IEEE mode also quiet each
+// input not known to be canonical, one more instruction per operand every
+// step.  In FP32 a v_med3 (against FLT_MAX, respectively 0) avoids that (a
+// med3 against +-inf is folded back into fmax/fmin); FP64 has no med3, so
+// v_max_f64 / v_min_f64 are written out.  (Inputs here are finite, or NaN in
+// a step the error test rejects anyway.)
 __device__ __forceinline__ float max_abs(float a, float b) {
     return __builtin_amdgcn_fmed3f(fabsf(a), fabsf(b), 3.40282347e38f);
 }
-__device__ __forceinline__ double max_abs(double a, double b) { return fmax(fabs(a), fabs(b)); }
+__device__ __forceinline__ double max_abs(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 __device__ __forceinline__ float min2(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
-__device__ __forceinline__ double min2(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ double min2(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 // ---------------------------------------------------------------------------
 // Persistent integrator.
