@@ -586,7 +586,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     // rays are shaded from a float azimuth, so a double one would be rounded
     // away at the end (about ten float additions per ray, ~1e-6 rad at most)
     T phi = T(0), phik = T(0);
-    int id = 0, attempts = 0, nsteps = 0, it = 0;
+    int id = 0, attempts = 0, it = 0;
     bool rej = false, refine = false, active = false;
     // prefetched next ray
     int pf_id = 0;
@@ -617,7 +617,6 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 phi = T(0);
                 phik = T(pf.y);
                 attempts = 0;
-                nsteps = 0;
                 it = 0;
                 rej = false;
                 refine = false;
@@ -676,7 +675,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // A trial step that would pass the next disk-plane crossing is
         // shortened to land on it exactly.
         const T phx = phi + hx;
-        const bool land = nrm && phx >= phik;
+        const bool land = nrm & (phx >= phik);
         const T ht = land ? phik - phi : hx;
         T vn, wn, gn, eu, ew;
         dp45<T>([k](T x) { return g_scaled<KAPPA>(k, x); }, v, w, g, ht, vn, wn, gn, eu, ew);
@@ -686,13 +685,15 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // proposal needs one reciprocal.
         const T su = fma(rtol, max_abs(v, vn), atol);
         const T sw = fma(rtol, max_abs(w, wn), atol);
-        const bool fits = fabs(eu) <= su && fabs(ew) <= sw;
+        const bool fits = (fabs(eu) <= su) & (fabs(ew) <= sw);
         const float fsu = (float)su, fsw = (float)sw;
-        const float err = fmaxf((float)fabs(eu) * fsw, (float)fabs(ew) * fsu) *
+        // |e| fs = |e fs| (fs > 0, rounding is sign-symmetric): the absolute
+        // values ride on the max as operand modifiers.
+        const float err = fmaxf(fabsf((float)eu * fsw), fabsf((float)ew * fsu)) *
                           __builtin_amdgcn_rcpf(fsu * fsw);
         const float fac = step_factor<T>(err);
-        const bool go = nrm && !capped;               // a trial step was taken
-        const bool acc = go && fits;
+        const bool go = nrm & !capped;               // a trial step was taken
+        const bool acc = go & fits;
         // Factor of the next trial step: fac clamped to [0.2, 5] after an
         // accepted step ([0.2, 1] right after a rejection) and to [0.2, inf)
         // after a rejected one, as one med3 with its upper bound selected (a
@@ -702,12 +703,12 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
 
         // Events of an accepted step, in order: disk, horizon, sky sphere.
         const T phin = land ? phik : phx;
-        const bool disk_hit = acc && land && vn >= vrout && vn <= vrin;
+        const bool disk_hit = acc & land & (vn >= vrout) & (vn <= vrin);
         // Horizon: u >= 1/(2M) is v >= 3/2, exact in either precision (+inf
         // for M = 0).
-        const bool capture = acc && !disk_hit && vn >= vh;
-        const bool skyx = acc && !disk_hit && !capture && vn <= vsky && wn < T(0);
-        const bool advance = acc && !disk_hit && !capture && !skyx;
+        const bool capture = acc & !disk_hit & (vn >= vh);
+        const bool skyx = acc & !disk_hit & !capture & (vn <= vsky) & (wn < T(0));
+        const bool advance = acc & !disk_hit & !capture & !skyx;
         // Newton on the step length for v(h) = v_sky (u = u_sky), redoing the
         // step from the last accepted state: h <- h - (v(h) - v_sky) / v'(h).
         // The accepted crossing step gives the first update; each refinement
@@ -716,8 +717,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         const T dh = (vn - vsky) * recip(wn);
         const T hh_new = ht - dh;
         const int it_new = refine ? it + 1 : 1;
-        const bool sky_done = newton && (fabs(dh) < ntol || it_new >= 4);
-        const bool over = advance && phin > max_phi;
+        const bool sky_done = newton & ((fabs(dh) < ntol) | (it_new >= 4));
+        const bool over = advance & (phin > max_phi);
 
         // State updates.
         if (go) {
@@ -725,7 +726,6 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             h = min2((acc && land) ? h : ht * T(f), hmax);
             rej = !acc;
         }
-        if (active && !capped) ++nsteps;
         if (acc && land && !disk_hit) phik += T(kPi);
         if (advance) {
             v = vn;
@@ -754,6 +754,10 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                                                : (double)s / (double)vn;
             if (R32) a.w.res32[id] = make_float2((float)pe, (float)rh);
             else a.w.res[id] = make_double2(pe, rh);
+            // Step evaluations: the trial steps, plus the Newton re-steps of a
+            // sky crossing (a ray in refinement ends only there; its last
+            // update is the it_new-th, the first came from the trial step).
+            const int nsteps = attempts + (sky_done ? it_new - 1 : 0);
             a.w.clst[id] = (int32_t)cls | (nsteps << 3);
             active = false;
         }
