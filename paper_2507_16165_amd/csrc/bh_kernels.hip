@@ -605,7 +605,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // start and fetch code then runs once for several finished rays
         // instead of on almost every step --------------------------------------
         const bool refill = __popcll(__ballot(!active)) >= refill_min || (drained && cnext >= cend);
-        if (refill && !active && pf_valid) {
+        if (refill & !active & pf_valid) {
             pf_valid = false;
             if (!VIRTUAL || pf.x == pf.x) {
                 id = pf_id;
@@ -669,8 +669,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         if (drained && cnext >= cend && __ballot(active || pf_valid) == 0) break;
 
         // ---- (B) one step evaluation per lane ------------------------------
-        const bool nrm = active && !refine;           // normal trial step
-        const bool capped = nrm && attempts >= max_steps;
+        const bool nrm = active & !refine;            // normal trial step
+        const bool capped = nrm & (attempts >= max_steps);
         const T hx = refine ? hh : h;
         // A trial step that would pass the next disk-plane crossing is
         // shortened to land on it exactly.
@@ -713,7 +713,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // step from the last accepted state: h <- h - (v(h) - v_sky) / v'(h).
         // The accepted crossing step gives the first update; each refinement
         // step gives one more (at most four updates).
-        const bool newton = (active && refine) || skyx;
+        const bool newton = (active & refine) | skyx;
         const T dh = (vn - vsky) * recip(wn);
         const T hh_new = ht - dh;
         const int it_new = refine ? it + 1 : 1;
@@ -723,10 +723,10 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // State updates.
         if (go) {
             ++attempts;
-            h = min2((acc && land) ? h : ht * T(f), hmax);
+            h = min2((acc & land) ? h : ht * T(f), hmax);
             rej = !acc;
         }
-        if (acc && land && !disk_hit) phik += T(kPi);
+        if (acc & land & !disk_hit) phik += T(kPi);
         if (advance) {
             v = vn;
             w = wn;
@@ -740,8 +740,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         }
 
         // A finished ray stores its result record.
-        if (capped || disk_hit || capture || sky_done || over) {
-            const uint8_t cls = (capped || over) ? UNRESOLVED
+        if (capped | disk_hit | capture | sky_done | over) {
+            const uint8_t cls = (capped | over) ? UNRESOLVED
                                 : disk_hit       ? DISK
                                 : capture        ? CAPTURED
                                                  : SKY;
