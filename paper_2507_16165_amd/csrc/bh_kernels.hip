@@ -716,7 +716,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         const bool newton = (active & refine) | skyx;
         const T dh = (vn - vsky) * recip(wn);
         const T hh_new = ht - dh;
-        const int it_new = refine ? it + 1 : 1;
+        // (it is 0 until a ray's first sky crossing: set at the ray's start,
+        // changed only by Newton updates, and a ray in refinement ends there)
+        const int it_new = it + 1;
         const bool sky_done = newton & ((fabs(dh) < ntol) | (it_new >= 4));
         const bool over = advance & (phin > max_phi);
 
