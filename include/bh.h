@@ -126,6 +126,12 @@ typedef struct {
                                 events located on the curve (the default)            */
     const struct bh_surrogate* surrogate; /* FP32 renders only: route eligible rays to this
                                 trained network (NULL = off; see bh_surrogate_*)     */
+    int    refill_fp32;      /* persistent integrator: a wavefront starts new FP32 rays
+                                once this many of its 64 lanes are idle (or its queue is
+                                dry); 1..64, 0 = auto (20).  Any value gives the same
+                                results; it only changes the schedule                 */
+    int    refill_fp64;      /* the same for the FP64 rays of FP64 mode; 0 = auto (6).
+                                (The critical band of FP32 mode always refills at 1.) */
 } bh_options;
 
 /* Optional per-ray outputs (device arrays of length n, any may be NULL).
@@ -143,7 +149,8 @@ typedef struct {
 
 /* Fills defaults: FP64, rtol 1e-10, atol 0 (-> rtol/r_sky), rtol_fp32 1e-6,
  * band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps 1e6, analytic capture
- * on, auto launch shape and batch groups.  Returns BH_ERR_ARG for NULL. */
+ * on, auto launch shape, refill thresholds and batch groups.  Returns BH_ERR_ARG
+ * for NULL. */
 bh_status bh_default_options(bh_options* opt);
 
 /* Traces n rays with world-space origins and directions (device, n*3 doubles
@@ -249,14 +256,18 @@ bh_status bh_surrogate_destroy(bh_surrogate* s);
  * floats).  Synchronous. */
 bh_status bh_surrogate_params(const bh_surrogate* s, int which, float* host_out, int64_t count);
 /* Replaces params (and Adam state if m, v are non-NULL; step = Adam step
- * count) from host arrays, e.g. to resume from a checkpoint.  Synchronous. */
+ * count) from host arrays, e.g. to resume from a checkpoint.  Synchronous.
+ * Clears the trust map's validity: renders do not route to the network
+ * again until bh_surrogate_build_trust or bh_surrogate_set_trust. */
 bh_status bh_surrogate_set_params(bh_surrogate* s, const float* host_params, const float* host_m,
                                   const float* host_v, int step);
 /* One training step on n samples (b, r0 in units of M; phi_exit = labelled
  * exit azimuth, NaN unless the ray escaped; captured = 0/1): forward, loss
  * (1/n) sum [escaped (y0 - t)^2 + 0.1 BCE(y1, captured)], backward and, if
  * hp->lr > 0, one Adam step.  loss (device float, may be NULL) receives the
- * loss before the step.  n is a multiple of 32 up to max_batch. */
+ * loss before the step.  n is a multiple of 32 up to max_batch.  A step with
+ * lr > 0 changes the parameters and so clears the trust map's validity, as
+ * bh_surrogate_set_params does. */
 bh_status bh_surrogate_train_step(bh_surrogate* s, const double* b, const double* r0,
                                   const double* phi_exit, const uint8_t* captured, int64_t n,
                                   const bh_adam* hp, float* loss, void* stream);

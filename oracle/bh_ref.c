@@ -508,26 +508,48 @@ void bhr_shade(const bhr_scene* sc, int cls, const double s[3], double r_hit, fl
     }
 }
 
+/* One image row: camera ray, trace and shade of every pixel in it. */
+static void render_row(const bhr_camera* cam, const bhr_scene* sc, const bhr_options* opt, int py,
+                       float* rgba, bhr_out* out)
+{
+    const int W = cam->width;
+    for (int px = 0; px < W; ++px) {
+        double o[3], d[3];
+        bhr_camera_ray(cam, px, py, o, d);
+        ray_result r;
+        trace_one(o, d, sc, opt, &r);
+        const int64_t i = (int64_t)py * W + px;
+        store(out, i, &r);
+        if (rgba) bhr_shade(sc, r.cls, r.exit_dir, r.r_hit, rgba + 4 * i);
+    }
+}
+
 int bhr_render_rows(const bhr_camera* cam, const bhr_scene* sc, const bhr_options* opt,
                     int row0, int row1, float* rgba, bhr_out* out)
 {
     if (!cam || !scene_ok(sc) || !opt) return -1;
     if (cam->width < 1 || cam->height < 1) return -1;
     if (row0 < 0 || row1 > cam->height || row0 > row1) return -1;
-    const int W = cam->width;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int py = row0; py < row1; ++py) {
-        for (int px = 0; px < W; ++px) {
-            double o[3], d[3];
-            bhr_camera_ray(cam, px, py, o, d);
-            ray_result r;
-            trace_one(o, d, sc, opt, &r);
-            const int64_t i = (int64_t)py * W + px;
-            store(out, i, &r);
-            if (rgba) bhr_shade(sc, r.cls, r.exit_dir, r.r_hit, rgba + 4 * i);
-        }
-    }
+    for (int py = row0; py < row1; ++py) render_row(cam, sc, opt, py, rgba, out);
     return 0;
+}
+
+int bhr_render_row_list(const bhr_camera* cam, const bhr_scene* sc, const bhr_options* opt,
+                        const int* rows, int nrows, float* rgba, bhr_out* out)
+{
+    if (!cam || !scene_ok(sc) || !opt || (!rows && nrows > 0) || nrows < 0) return -1;
+    if (cam->width < 1 || cam->height < 1) return -1;
+    for (int k = 0; k < nrows; ++k)
+        if (rows[k] < 0 || rows[k] >= cam->height) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nrows; ++k) render_row(cam, sc, opt, rows[k], rgba, out);
+    return 0;
+}
+
+void bhr_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -118,6 +118,15 @@ int bhr_trace_rays(const double* origin, const double* dir, int64_t n,
 int bhr_render_rows(const bhr_camera* cam, const bhr_scene* sc, const bhr_options* opt,
                     int row0, int row1, float* rgba, bhr_out* out);
 
+/* Render the listed image rows (each 0 <= rows[k] < height; OpenMP over the
+ * list, one row per task).  Same per-pixel computation as bhr_render_rows;
+ * arrays are full-image as there. */
+int bhr_render_row_list(const bhr_camera* cam, const bhr_scene* sc, const bhr_options* opt,
+                        const int* rows, int nrows, float* rgba, bhr_out* out);
+
+/* Number of OpenMP threads later batch calls use (n >= 1). */
+void bhr_set_threads(int n);
+
 /* Colour of one ray from its class, end vector and hit radius. */
 void bhr_shade(const bhr_scene* sc, int cls, const double exit_dir[3], double r_hit, float rgba[4]);
 /* Bilinear sample of the sky image at direction angles (theta, varphi):

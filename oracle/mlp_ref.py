@@ -21,6 +21,11 @@ and initial conditions give the labels, see bh_ref.c):
               c_i = 1 for captured rays;
   - Adam (Kingma & Ba 2015) on FP32 master weights; the network runs on the
     bf16-rounded copy.
+  - quantize=True: the network as it is stored between layers -- the hidden
+    activations h1, h2, h3, the output gradient dL/dy and the back-propagated
+    gradients dL/dz3, dL/dz2, dL/dz1 each rounded to bf16 (ties to even)
+    where the matrix-core network keeps them; every sum is still FP64.  With
+    quantize=False (the default) nothing but the weights is rounded.
 All lengths in units of M (the method is scale-free in M).
 """
 from __future__ import annotations
@@ -105,17 +110,22 @@ def bf16_round(x):
 
 # -- network ------------------------------------------------------------------
 
-def forward(params, x):
+def _q(x, quantize):
+    """x rounded to bf16 (through float32) when quantize, else x itself."""
+    return bf16_round(np.asarray(x, np.float64).astype(np.float32)).astype(np.float64) if quantize else x
+
+
+def forward(params, x, quantize=False):
     """Returns (y, cache); params: [W1, b1, ..., W4, b4] (any float dtype,
-    evaluated in float64)."""
+    evaluated in float64); quantize: hidden activations rounded to bf16."""
     W = [np.asarray(p, np.float64) for p in params]
     h0 = np.asarray(x, np.float64)
     z1 = h0 @ W[0] + W[1]
-    h1 = np.maximum(z1, 0.0)
+    h1 = _q(np.maximum(z1, 0.0), quantize)
     z2 = h1 @ W[2] + W[3]
-    h2 = np.maximum(z2, 0.0)
+    h2 = _q(np.maximum(z2, 0.0), quantize)
     z3 = h2 @ W[4] + W[5]
-    h3 = np.maximum(z3, 0.0)
+    h3 = _q(np.maximum(z3, 0.0), quantize)
     y = h3 @ W[6] + W[7]
     return y, (h0, z1, h1, z2, h2, z3, h3)
 
@@ -137,20 +147,24 @@ def loss_and_dy(y, t, escaped, captured):
     return L, dy
 
 
-def backward(params, cache, dy):
-    """Gradients [dW1, db1, ..., dW4, db4] (float64) of sum(dy * y)."""
+def backward(params, cache, dy, quantize=False):
+    """Gradients [dW1, db1, ..., dW4, db4] (float64) of sum(dy * y);
+    quantize: dy and the back-propagated dz rounded to bf16 (the ReLU masks
+    then come from the stored activations, h > 0)."""
     W = [np.asarray(p, np.float64) for p in params]
     h0, z1, h1, z2, h2, z3, h3 = cache
+    m1, m2, m3 = (h1 > 0, h2 > 0, h3 > 0) if quantize else (z1 > 0, z2 > 0, z3 > 0)
+    dy = _q(np.asarray(dy, np.float64), quantize)
     g = [None] * 8
     g[6] = h3.T @ dy
     g[7] = dy.sum(0)
-    dz3 = (dy @ W[6].T) * (z3 > 0)
+    dz3 = _q((dy @ W[6].T) * m3, quantize)
     g[4] = h2.T @ dz3
     g[5] = dz3.sum(0)
-    dz2 = (dz3 @ W[4].T) * (z2 > 0)
+    dz2 = _q((dz3 @ W[4].T) * m2, quantize)
     g[2] = h1.T @ dz2
     g[3] = dz2.sum(0)
-    dz1 = (dz2 @ W[2].T) * (z1 > 0)
+    dz1 = _q((dz2 @ W[2].T) * m1, quantize)
     g[0] = h0.T @ dz1
     g[1] = dz1.sum(0)
     return g

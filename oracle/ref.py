@@ -76,6 +76,10 @@ def lib():
                                      C.POINTER(Options), C.POINTER(Out)]
         L.bhr_render_rows.argtypes = [C.POINTER(Camera), C.POINTER(Scene), C.POINTER(Options),
                                       C.c_int, C.c_int, C.c_void_p, C.POINTER(Out)]
+        L.bhr_render_row_list.argtypes = [C.POINTER(Camera), C.POINTER(Scene), C.POINTER(Options),
+                                          C.c_void_p, C.c_int, C.c_void_p, C.POINTER(Out)]
+        L.bhr_set_threads.argtypes = [C.c_int]
+        L.bhr_set_threads.restype = None
         L.bhr_shade.argtypes = [C.POINTER(Scene), C.c_int, C.c_void_p, C.c_double, C.c_void_p]
         L.bhr_sky_sample.argtypes = [C.POINTER(Scene), C.c_double, C.c_double, C.c_void_p]
         L.bhr_sky_sample.restype = None
@@ -172,6 +176,26 @@ def render(cam: Camera, sc: Scene, opt: Options | None = None, rows=None):
     if rc != 0:
         raise ValueError("bhr_render_rows rejected its arguments")
     return rgba, r
+
+
+def render_row_list(cam: Camera, sc: Scene, rows, opt: Options | None = None):
+    """Render the listed rows in one call (OpenMP over the list).  Returns
+    (rgba HxWx4 float32, Rays over the full image; unlisted rows are zero)."""
+    opt = opt or options()
+    W, H = cam.width, cam.height
+    rows = np.ascontiguousarray(rows, dtype=np.int32).ravel()
+    rgba = np.zeros((H, W, 4), np.float32)
+    r, out = _alloc(W * H)
+    rc = lib().bhr_render_row_list(C.byref(cam), C.byref(sc), C.byref(opt), rows.ctypes.data,
+                                   int(rows.size), rgba.ctypes.data, C.byref(out))
+    if rc != 0:
+        raise ValueError("bhr_render_row_list rejected its arguments")
+    return rgba, r
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's batch loops from now on."""
+    lib().bhr_set_threads(int(n))
 
 
 def camera_rays(cam: Camera, pixels=None):

@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
                 ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
                 ("samples_side", C.c_int), ("batch_groups", C.c_int), ("fixed_eps", C.c_double),
-                ("surrogate", C.c_void_p)]
+                ("surrogate", C.c_void_p), ("refill_fp32", C.c_int), ("refill_fp64", C.c_int)]
 
 
 class Request(C.Structure):

@@ -191,6 +191,8 @@ bh_status check_opt(const bh_options* o) {
     if (o->grid_blocks < 0 || o->chunk < 0 || o->batch_groups < 0)
         return fail(BH_ERR_ARG, "launch shape and batch groups must be >= 0");
     if (o->chunk % 64 != 0) return fail(BH_ERR_ARG, "chunk must be a multiple of 64");
+    if (o->refill_fp32 < 0 || o->refill_fp32 > 64 || o->refill_fp64 < 0 || o->refill_fp64 > 64)
+        return fail(BH_ERR_ARG, "refill thresholds must be in [0, 64]");
     return BH_OK;
 }
 
@@ -234,6 +236,12 @@ bh::DevTol dev_tol(const bh_options* o, const bh_scene* sc) {
     t.newton64 = 1e-15;
     t.newton32 = 1e-3f;
     t.max_steps = o->max_steps;
+    // Lazy refill: a wavefront starts new rays once this many lanes are idle
+    // (or its queue is dry).  ~3-4 steps' worth of finished rays: FP32 rays
+    // take ~11 step evaluations, FP64 rays ~60; measured on the 4K orbit,
+    // 20 and 6 took ~5% less integrator time than 1.
+    t.refill32 = o->refill_fp32 > 0 ? o->refill_fp32 : 20;
+    t.refill64 = o->refill_fp64 > 0 ? o->refill_fp64 : 6;
     return t;
 }
 

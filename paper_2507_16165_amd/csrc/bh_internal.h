@@ -67,6 +67,7 @@ struct DevTol {
     double newton64;          // Newton stop on |dh| for the sky crossing
     float newton32;
     int max_steps;
+    int refill32, refill64;   // idle lanes a wavefront waits for before starting rays (1..64)
 };
 
 // Camera basis for one frame, computed once per frame by the host runtime.

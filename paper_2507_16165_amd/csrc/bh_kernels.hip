@@ -521,12 +521,9 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Idle lanes a wavefront waits for before it starts new rays: about the
-// lanes that finish in 3-4 steps (FP32 rays take ~11 step evaluations, FP64
-// rays ~60).  Measured on the 4K orbit: 20 and 6 against 1, about 5% less
-// integrator time each.  The FP64 critical band, whose rays are long, refills
-// at once.
-constexpr int kRefill32 = 20, kRefill64 = 6;
+// Idle lanes a wavefront waits for before it starts new rays come from the
+// options (DevTol::refill32 / refill64; defaults 20 and 6).  The FP64
+// critical band of FP32 mode, whose rays are long, refills at once.
 
 // Drains one queue.  VIRTUAL: the queue is the index range [0, total) and
 // the start records come from rec[id] (w0 = NaN: the ray is not for this
@@ -792,7 +789,7 @@ __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     run_queue<double, true, BATCH, false, KAPPA>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
                                                  kSlices, a.tol.rtol64, a.tol.newton64, bct,
-                                                 kRefill64);
+                                                 a.tol.refill64);
 }
 
 // FP32 mode (batches keep FP32 records).  The first `band_blocks` blocks
@@ -815,7 +812,7 @@ __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_bloc
     }
     run_queue<float, true, BATCH, BATCH, KAPPA>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
                                                 kSlices, a.tol.rtol32, a.tol.newton32, bct,
-                                                kRefill32);
+                                                a.tol.refill32);
 }
 
 template <bool KAPPA>

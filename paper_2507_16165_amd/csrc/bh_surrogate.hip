@@ -907,6 +907,9 @@ bh_status bh_surrogate_set_params(bh_surrogate* s, const float* params, const fl
     if (m) HIPCHK(hipMemcpy(s->m, m, NPARAM * 4, hipMemcpyHostToDevice), "upload");
     if (v) HIPCHK(hipMemcpy(s->v, v, NPARAM * 4, hipMemcpyHostToDevice), "upload");
     s->step = step;
+    // the trust map was validated on the old parameters: renders stop routing
+    // to the network until a map is built (or set) for these
+    s->trusted = 0;
     HIPCHK(repack(s, nullptr), "pack");
     HIPCHK(hipDeviceSynchronize(), "sync");
     return BH_OK;
@@ -975,6 +978,7 @@ bh_status bh_surrogate_train_step(bh_surrogate* s, const double* b, const double
     HIPCHK(hipGetLastError(), "assemble");
     if (hp && hp->lr > 0.0f) {
         s->step += 1;
+        s->trusted = 0;  // new parameters: the trust map no longer applies
         const float c1 = 1.0f / (1.0f - powf(hp->beta1, (float)s->step));
         const float c2 = 1.0f / (1.0f - powf(hp->beta2, (float)s->step));
         k_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(NPARAM, s->P, s->G, s->m, s->v, hp->lr,

@@ -73,6 +73,8 @@ def test_render_rejects_null_and_bad_options():
     assert _render(cam, sc, api.options(samples_side=-1)) == api.BH_ERR_ARG
     assert _render(cam, sc, api.options(batch_groups=-1)) == api.BH_ERR_ARG
     assert _render(cam, sc, api.options(fixed_eps=-1.0)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(refill_fp32=65)) == api.BH_ERR_ARG
+    assert _render(cam, sc, api.options(refill_fp64=-1)) == api.BH_ERR_ARG
     assert _render(cam, sc, api.options(fixed_eps=0.5, precision=api.FP32)) == api.BH_ERR_UNSUPPORTED
     L = api.lib()
     assert L.bh_render(None, None, None, None, None, None) == api.BH_ERR_ARG
@@ -144,3 +146,29 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """The binding's ctypes structures have the field offsets and sizes the C
+    compiler gives the structs of include/bh.h (a field added on one side
+    only would shift every later field)."""
+    import subprocess
+    structs = {"bh_scene": api.Scene, "bh_camera": api.Camera, "bh_options": api.Options,
+               "bh_ray_out": api.RayOut, "bh_request": api.Request,
+               "bh_batch_summary": api.BatchSummary, "bh_adam": api.Adam}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bh.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        py = structs[cname]
+        want = C.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(val) == want, (cname, field, int(val), want)

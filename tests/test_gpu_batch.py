@@ -69,6 +69,40 @@ def test_batch_equals_per_request_renders(bh, precision, graph):
     b.close()
 
 
+@pytest.mark.parametrize("precision,graph", [("fp32", True), ("fp64", False)])
+def test_batch_matches_oracle(bh, ref, precision, graph):
+    """Batched images against the CPU oracle directly: the 8 mixed small
+    requests (every pixel) and every 32nd request of the 512-request serving
+    mix at its real resolution (128^2 .. 2048^2; 12 rows spread over each
+    image), traced together as one batch.  Batches return images only, so
+    the comparison is by colour outside the ambiguity zones (critical band
+    within 1e-3 M of b_c, checker edges, disk edges read back from the disk
+    colour); elsewhere a class or exit error beyond the path's bound changes
+    the colour and fails."""
+    import torch
+    from parity import compare_image
+    from test_gpu_parity import ref_camera, ref_scene
+    frames = mixed_frames() + inputs.serving_batch(512)[::32]
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    b = bh.Batch(frames, bh.options(precision=p), use_graph=graph)
+    b.launch()
+    torch.cuda.synchronize()
+    compared = 0
+    for k, (f, img) in enumerate(zip(frames, b.images)):
+        W, H = f.camera.width, f.camera.height
+        small = W * H <= 250 * 250
+        rows = list(range(H)) if small else sorted(set(np.linspace(0, H - 1, 12).astype(int)))
+        r_rgba, r_rays = ref.render_row_list(ref_camera(ref, f.camera), ref_scene(ref, f.scene), rows)
+        mask = np.zeros(W * H, bool)
+        for r0 in rows:
+            mask[r0 * W:(r0 + 1) * W] = True
+        compared += compare_image(r_rgba, r_rays, img.cpu().numpy(), f.scene, precision, mask=mask,
+                                  sky_tex=f.scene.sky_tex)
+    b.close()
+    print(f"{len(frames)} requests, {compared} pixels compared with the oracle")
+    assert compared > 100_000
+
+
 def edge_frames():
     """Requests at the edges of the scene constants: flat space (M = 0: no
     horizon, an infinite FP32 horizon threshold), a camera at 400 M with a
@@ -226,12 +260,26 @@ def test_serving_batch_runs_and_reports(bh):
 
 
 def test_autotune_returns_a_candidate(bh, tmp_path):
+    """The tuner times every knob (grid, chunk, refill threshold, groups)
+    with device events, caches its pick, reuses the cache, and its pick
+    renders the same pixels as the defaults."""
+    import torch
     from paper_2507_16165_amd import autotune
     frames = mixed_frames()
     path = tmp_path / "tune.json"
-    best = autotune.tune_batch(frames, bh.FP32, "mixed_small", cache_path=str(path), reps=1)
+    best = autotune.tune_batch(frames, bh.FP32, "mixed_small", cache_path=str(path), reps=3)
     assert best["chunk"] in autotune.CHUNKS and best["grid_blocks"] > 0
+    assert best["refill"] in autotune.REFILLS_FP32 or best["refill"] == 20
+    assert best["batch_groups"] in autotune.GROUPS or best["batch_groups"] == 0
+    assert best["candidates_timed"] >= len(autotune.BLOCKS_PER_CU) + len(autotune.CHUNKS)
     cached = json.loads(path.read_text())
     assert list(cached.values())[0] == best
     # the cached entry is reused
     assert autotune.tune_batch(frames, bh.FP32, "mixed_small", cache_path=str(path)) == best
+    want = _single(bh, frames, bh.FP32)
+    b = bh.Batch(frames, autotune.options_for(best, bh.FP32), use_graph=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for k, (img, ref) in enumerate(zip(b.images, want)):
+        np.testing.assert_array_equal(img.cpu().numpy(), ref, err_msg=f"request {k}")
+    b.close()

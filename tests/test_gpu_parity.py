@@ -46,23 +46,16 @@ def gpu_render(bh, frame, precision, **kw):
 
 
 def oracle_rows(ref, frame, rows, rtol=1e-10):
-    """Oracle on a set of image rows (full image arrays; other rows zero)."""
+    """Oracle on a set of image rows, one call over the list (OpenMP across
+    the rows); full-image arrays, other rows zero."""
     cam, sc = ref_camera(ref, frame.camera), ref_scene(ref, frame.scene)
     W, H = frame.camera.width, frame.camera.height
-    rgba = np.zeros((H, W, 4), np.float32)
+    rows = sorted(set(int(r) for r in rows))
+    rgba, rays = ref.render_row_list(cam, sc, rows, ref.options(rtol=rtol))
     mask = np.zeros(H * W, bool)
-    acc = None
     for r0 in rows:
-        img, rays = ref.render(cam, sc, ref.options(rtol=rtol), rows=(r0, r0 + 1))
-        rgba[r0] = img[r0]
-        sl = slice(r0 * W, (r0 + 1) * W)
-        mask[sl] = True
-        if acc is None:
-            acc = rays
-        else:
-            for f in ("cls", "b", "phi_end", "exit_dir", "r_hit", "n_acc", "n_rej", "e_drift"):
-                getattr(acc, f)[sl] = getattr(rays, f)[sl]
-    return rgba, acc, mask
+        mask[r0 * W:(r0 + 1) * W] = True
+    return rgba, rays, mask
 
 
 # ---------------------------------------------------------------------------
@@ -102,6 +95,28 @@ def test_disk_frame_fp32_band(bh, ref, size):
     assert np.all(out["path"][band] == bh.PATH_FP64)
     assert np.all(out["path"][~band & (out["path"] != bh.PATH_NONE)] == bh.PATH_FP32)
     assert s["max_angle"] <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("disk", [None, (6.0, 20.0)])
+def test_band_rays_match_oracle(bh, ref, precision, disk):
+    """A 512x512 frame framed on the shadow edge (camera at 30 M, FOV 21 deg):
+    about 7,000 rays lie in the critical band 1e-3 M <= |b - b_c| < 0.05 M.
+    They go through the FP64 integrator in both modes (in FP32 mode through
+    its separate band queue), and each is held to the oracle: classes agree
+    (outside a disk-edge zone widened by the band bound), end azimuths and
+    exit directions within 1e-8 + b 1e-10 / |b - b_c| (FP32 mode: exit
+    directions are mapped in FP32, so within 1e-4 plus that), disk radii
+    likewise, colours outside the checker-edge zone."""
+    f = inputs.Frame(inputs.Camera(30.0, 75.0, 20.0, 21.0, 512, 512), inputs.scene_in_m(1.0, disk))
+    rgba, out = gpu_render(bh, f, bh.FP64 if precision == "fp64" else bh.FP32)
+    r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
+    s = compare(r_rays, out, f.scene, precision)
+    assert s["band_compared"] > 6000, s
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, precision)
+    band = np.abs(r_rays.b - B_CRIT) < 0.05
+    assert np.all(out["path"][band] == bh.PATH_FP64)
+    print(f"band rays compared {s['band_compared']}, max end-azimuth difference {s['max_band_phi']:.3g} rad")
 
 
 @pytest.mark.parametrize("k", [0, 7])
@@ -189,17 +204,22 @@ def test_flat_space_render(bh, ref, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_schedule_invariance(bh, precision):
-    """Each ray's arithmetic is independent of the launch shape and queue
-    order: results are bit-identical across grid sizes and chunk sizes (the
-    race test for the work queue)."""
+    """Each ray's arithmetic is independent of the launch shape, the queue
+    order and the refill threshold: results are bit-identical across grid
+    sizes, chunk sizes and refill thresholds 1 (every finished lane restarts
+    at once: the stress case for the queue), 6, 20 and 32 (the race test for
+    the work queue)."""
     f = inputs.disk_1024(256)
     p = bh.FP64 if precision == "fp64" else bh.FP32
     base_rgba, base = gpu_render(bh, f, p)
-    for g, c in [(1, 64), (7, 64), (64, 1024), (3, 192)]:
-        rgba, out = gpu_render(bh, f, p, grid_blocks=g, chunk=c)
-        np.testing.assert_array_equal(rgba, base_rgba)
+    shapes = [dict(grid_blocks=g, chunk=c) for g, c in [(1, 64), (7, 64), (64, 1024), (3, 192)]]
+    shapes += [dict(refill_fp32=r, refill_fp64=r) for r in (1, 6, 20, 32)]
+    shapes += [dict(grid_blocks=5, chunk=64, refill_fp32=1, refill_fp64=1)]
+    for kw in shapes:
+        rgba, out = gpu_render(bh, f, p, **kw)
+        np.testing.assert_array_equal(rgba, base_rgba, err_msg=str(kw))
         for k in ("cls", "phi_end", "r_hit", "steps", "path"):
-            np.testing.assert_array_equal(out[k], base[k])
+            np.testing.assert_array_equal(out[k], base[k], err_msg=f"{kw} {k}")
 
 
 def test_step_caps(bh, ref):

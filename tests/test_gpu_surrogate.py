@@ -69,10 +69,36 @@ def test_inference_matches_oracle_forward(bh, rand_params):
     sur.close()
 
 
+def _clear_batch(params, n, seed, margin=2e-3):
+    """n training samples (b, r0) whose pre-activations, in the bf16-rounded
+    network, all lie at least `margin` of their layer's RMS away from zero.
+    A ReLU's gradient jumps at zero, so a unit whose input sits within
+    rounding of it could switch between the FP32-accumulating GPU and the
+    FP64 oracle and change its sample's whole contribution; the comparison
+    is made away from those points."""
+    b, r0 = _batch(8 * n, seed)
+    _, c = R.forward(params, R.features(b, r0), quantize=True)
+    clear = np.ones(b.size, bool)
+    for z in (c[1], c[3], c[5]):
+        clear &= np.all(np.abs(z) >= margin * np.sqrt(np.mean(z * z)), axis=1)
+    idx = np.nonzero(clear)[0]
+    assert idx.size >= n
+    return b[idx[:n]], r0[idx[:n]]
+
+
 def test_gradients_and_adam_match_oracle(bh, rand_params):
+    """Gradients of one training step against the oracle's, element by
+    element: |g - g_ref| <= 1e-2 max|g_ref| for every entry of every tensor,
+    where g_ref is the FP64 network that rounds to bf16 where the GPU network
+    stores bf16 values (hidden activations, output and back-propagated
+    gradients) -- the GPU then differs only by FP32 accumulation order.
+    Against the plain FP64 network (nothing rounded but the weights) the
+    gradients agree to 4% in norm per tensor, the size of the bf16 storage
+    effect.  Then one Adam step against the oracle's update."""
     import torch
     sur = bh.Surrogate(rand_params, max_batch=1024)
-    b, r0 = _batch(512, 2)
+    pr = [R.bf16_round(x) for x in split(rand_params)]
+    b, r0 = _clear_batch(pr, 512, 2)
     rng = np.random.default_rng(3)
     esc = b > B_CRIT
     phi = np.where(esc, R.predict_exit(b, r0, rng.normal(size=b.size)), np.nan)
@@ -80,15 +106,24 @@ def test_gradients_and_adam_match_oracle(bh, rand_params):
     loss = torch.zeros(1, device="cuda")
     sur.train_step(_t(b), _t(r0), _t(phi), _t(cap), 0.0, loss)  # lr = 0: gradient only
     torch.cuda.synchronize()
-    pr = [R.bf16_round(x) for x in split(rand_params)]
-    y, cache = R.forward(pr, R.features(b, r0))
     e = R.regression_mask(b, phi).astype(float)
-    L, dy = R.loss_and_dy(y, R.targets(b, r0, phi), e, cap.astype(float))
+    tgt = R.targets(b, r0, phi)
+    yq, cq = R.forward(pr, R.features(b, r0), quantize=True)
+    Lq, dyq = R.loss_and_dy(yq, tgt, e, cap.astype(float))
+    gq = R.backward(pr, cq, dyq, quantize=True)
+    y, cache = R.forward(pr, R.features(b, r0))
+    L, dy = R.loss_and_dy(y, tgt, e, cap.astype(float))
     gref = R.backward(pr, cache, dy)
+    assert abs(loss.item() / Lq - 1.0) < 1e-3, (loss.item(), Lq)
     assert abs(loss.item() / L - 1.0) < 1e-2
-    for k, (g, gr) in enumerate(zip(split(sur.get(1)), gref)):
-        rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
-        assert rel < 4e-2, (k, rel)  # bf16 activations and output gradients
+    worst = []
+    for k, (g, gr, gp) in enumerate(zip(split(sur.get(1)), gq, gref)):
+        err = np.abs(g - gr).max() / np.abs(gr).max()
+        worst.append(err)
+        assert err <= 1e-2, (k, err)
+        rel = np.linalg.norm(g - gp) / np.linalg.norm(gp)
+        assert rel < 4e-2, (k, rel)  # bf16 activations and gradients
+    print("largest element error over max|g_ref| per tensor:", ["%.2e" % w for w in worst])
     np.testing.assert_array_equal(sur.get(0), rand_params)  # lr = 0 left the weights alone
     # one Adam step, checked against the oracle's update with the GPU's gradient
     p0 = sur.get(0)
@@ -171,31 +206,79 @@ def _render(bh, frame, sur=None):
     return rgba.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("k", [3, 9])
-def test_render_with_surrogate_matches_oracle(bh, trained, ref, k):
-    """4K orbit frames with the surrogate: surrogate-routed rays exist and every
-    ray (surrogate or integrator) meets the FP32 path's bounds on sampled rows."""
+def test_render_with_surrogate_matches_oracle(bh, trained, ref):
+    """4K orbit frames with the surrogate, held to the oracle where the
+    network serves rays.  The frame with the largest surrogate share is
+    rendered (FP32 + band + surrogate), the 12 rows holding the most
+    surrogate-served pixels are traced by the oracle, and every ray in them
+    meets the FP32 path's bounds; at least 1000 of them were served by the
+    network, each within 1e-4 rad of the oracle's exit direction."""
+    from parity import angle_between
     from test_gpu_parity import oracle_rows
     sur, _ = trained
-    f = inputs.orbit_4k()[k]
+    frames = inputs.orbit_4k()
+    shares = []
+    for f in frames:
+        opt = bh.options(precision=bh.FP32)
+        opt.surrogate = sur.handle
+        bh.render(f.camera, f.scene, opt)
+        shares.append(bh.last_counts()["surrogate"])
+    k = int(np.argmax(shares))
+    f = frames[k]
     rgba, out = _render(bh, f, sur)
-    n_sur = int((out["path"] == bh.PATH_SURROGATE).sum())
-    print(f"frame {k}: r/M = {f.camera.r / f.scene.M:.1f}, surrogate rays {n_sur}", flush=True)
-    H = f.camera.height
-    rows = sorted(set(np.linspace(0, H - 1, 9).astype(int)))
+    on_img = (out["path"] == bh.PATH_SURROGATE).reshape(f.camera.height, f.camera.width)
+    per_row = on_img.sum(1)
+    rows = sorted(np.argsort(per_row)[::-1][:12].tolist())
+    print(f"frame {k}: r/M = {f.camera.r / f.scene.M:.1f}, surrogate rays {int(on_img.sum())}, "
+          f"in the compared rows {int(per_row[rows].sum())}", flush=True)
     _, r_rays, mask = oracle_rows(ref, f, rows)
     s = compare(r_rays, out, f.scene, "fp32", mask=mask)
     on = mask & (out["path"] == bh.PATH_SURROGATE)
-    if on.any():
-        from parity import angle_between
-        assert angle_between(r_rays.exit_dir[on], out["exit_dir"][on]).max() <= 1e-4
+    assert on.sum() >= 1000, int(on.sum())
+    assert np.all(r_rays.cls[on] == ref.SKY)
+    err = angle_between(r_rays.exit_dir[on], out["exit_dir"][on])
+    print(f"surrogate rays compared {int(on.sum())}, max exit error {err.max():.3g} rad", flush=True)
+    assert err.max() <= 1e-4
     assert s["max_angle"] <= 1e-4
+
+
+def test_new_parameters_invalidate_the_trust_map(bh, trained):
+    """A render routes rays to the network only while its trust map was
+    built for the current parameters: after set_params or a training step
+    with lr > 0 no ray is served until the map is set again."""
+    import torch
+    sur, _ = trained
+    f = max(inputs.orbit_4k(), key=lambda fr: fr.camera.r / fr.scene.M)
+    opt = bh.options(precision=bh.FP32)
+    opt.surrogate = sur.handle
+    bh.render(f.camera, f.scene, opt)
+    assert bh.last_counts()["surrogate"] > 0
+    params, m, v, trust = sur.get(0), sur.get(2), sur.get(3), sur.trust()
+    sur.set(params, m, v)
+    bh.render(f.camera, f.scene, opt)
+    assert bh.last_counts()["surrogate"] == 0
+    sur.set_trust(trust)
+    bh.render(f.camera, f.scene, opt)
+    assert bh.last_counts()["surrogate"] > 0
+    b, r0 = _batch(64, 9)
+    phi = np.full(64, np.nan)
+    cap = (b < B_CRIT).astype(np.uint8)
+    sur.train_step(_t(b), _t(r0), _t(phi), _t(cap), 1e-9)
+    torch.cuda.synchronize()
+    bh.render(f.camera, f.scene, opt)
+    assert bh.last_counts()["surrogate"] == 0
+    sur.set(params, m, v)  # restore the trained network and its map for later tests
+    sur.set_trust(trust)
 
 
 def test_surrogate_gain(bh, trained):
     """What the trained network gains over the integrator alone on the 16-frame
-    4K orbit (FP32 + band both ways): prints the measured ratio of throughputs
-    (it may be below 1) and checks the share of rays the network served."""
+    4K orbit (FP32 + band both ways, one render call per frame): prints the
+    measured ratio of throughputs, which may be below 1 -- the network costs
+    66,560 FLOP per ray against about 1 kFLOP for the FP32 integrator on the
+    far rays it can serve -- and checks that the network served a real share
+    of the rays (at least 5%) while the images' classes stayed those of the
+    integrator alone outside the critical band."""
     import torch
     sur, _ = trained
     frames = inputs.orbit_4k()
@@ -222,4 +305,12 @@ def test_surrogate_gain(bh, trained):
     print(f"surrogate gain: integrator {res['integrator']:.0f} Mrays/s, with surrogate "
           f"{res['surrogate']:.0f} Mrays/s, ratio {res['surrogate'] / res['integrator']:.3f}, "
           f"surrogate share {share:.3f}", flush=True)
-    assert share > 0.0
+    assert share > 0.05
+    f = max(frames, key=lambda fr: fr.camera.r / fr.scene.M)
+    opt = bh.options(precision=bh.FP32)
+    _, a = bh.render(f.camera, f.scene, opt, fields=("cls", "b"))
+    opt.surrogate = sur.handle
+    _, b = bh.render(f.camera, f.scene, opt, fields=("cls", "path"))
+    clear = (a["b"] - B_CRIT * f.scene.M).abs() >= 0.05 * f.scene.M
+    assert bool((b["path"] == bh.PATH_SURROGATE).any())
+    assert torch.equal(a["cls"][clear], b["cls"][clear])

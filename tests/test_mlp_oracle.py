@@ -109,3 +109,67 @@ def test_first_order_sweep_is_weak_field_accurate():
         r0 = 180.0 if b < 180 else 400.0
         exact = Q.exit_phi(1.0, b, r0, R.R_SKY, True)
         assert abs(R.sweep_first_order(b, r0) - exact) < 3 * (15 * math.pi / 4) / b**2
+
+
+def _dyadic_network(rng):
+    """A network whose every activation and back-propagated gradient is exact
+    in bf16: each unit reads exactly one unit of the layer below, through a
+    power-of-two weight, with zero biases (scaled permutations), so values
+    stay signed powers of two times the dyadic inputs."""
+    params = []
+    for k, (fi, fo) in enumerate(R.SHAPES):
+        W = np.zeros((fi, fo), np.float32)
+        src = rng.permutation(fo) % fi if fi < fo else rng.permutation(fi)[:fo]
+        for j in range(fo):
+            W[src[j], j] = rng.choice([-1.0, 1.0]) * 2.0 ** int(rng.integers(-2, 3))
+        params += [W, np.zeros(fo, np.float32)]
+    return params
+
+
+def test_quantized_network_is_exact_where_nothing_rounds():
+    """quantize=True only rounds: on a network and batch whose activations
+    and gradients are all exact bf16 values it gives the same forward and
+    backward bit for bit as the plain FP64 network."""
+    rng = np.random.default_rng(3)
+    p = _dyadic_network(rng)
+    x = rng.choice([-1.0, -0.5, 0.25, 0.75, 1.5], size=(64, 2))
+    dy = rng.choice([-2.0, -0.125, 0.0, 0.5, 1.0], size=(64, 2))
+    y0, c0 = R.forward(p, x)
+    y1, c1 = R.forward(p, x, quantize=True)
+    np.testing.assert_array_equal(y0, y1)
+    g0 = R.backward(p, c0, dy)
+    g1 = R.backward(p, c1, dy, quantize=True)
+    for a, b in zip(g0, g1):
+        np.testing.assert_array_equal(a, b)
+    assert any(np.abs(a).max() > 0 for a in g0)
+
+
+def test_quantized_network_rounds_at_bf16_precision():
+    """On a random network the rounded activations move the outputs by about
+    bf16 precision (2^-9 relative per stored value).  Gradients move more: a
+    ReLU whose input lies within rounding of zero can switch, and a switched
+    unit changes its sample's whole contribution.  Away from such samples
+    (every pre-activation at least 1e-2 of its layer's RMS from zero) the
+    gradients too differ by about bf16 precision."""
+    rng = np.random.default_rng(4)
+    p = [R.bf16_round(a) for a in R.init_params(5)]
+    for k in (1, 3, 5, 7):
+        p[k] = R.bf16_round(rng.normal(scale=0.1, size=p[k].shape).astype(np.float32))
+    x = rng.normal(size=(2048, 2))
+    dy = rng.normal(size=(2048, 2)) / 256
+    y0, c0 = R.forward(p, x)
+    y1, c1 = R.forward(p, x, quantize=True)
+    rel = np.abs(y1 - y0).max() / np.abs(y0).max()
+    assert 1e-5 < rel < 2e-2, rel
+    for a, b in zip(R.backward(p, c0, dy), R.backward(p, c1, dy, quantize=True)):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+        assert 1e-5 < rel < 0.2, rel
+    clear = np.ones(x.shape[0], bool)
+    for z in (c0[1], c0[3], c0[5]):
+        clear &= np.all(np.abs(z) >= 1e-2 * np.sqrt(np.mean(z * z)), axis=1)
+    assert clear.sum() > 50
+    y0, c0 = R.forward(p, x[clear])
+    y1, c1 = R.forward(p, x[clear], quantize=True)
+    for a, b in zip(R.backward(p, c0, dy[clear]), R.backward(p, c1, dy[clear], quantize=True)):
+        rel = np.abs(a - b).max() / np.abs(a).max()
+        assert rel < 2e-2, rel

@@ -268,6 +268,39 @@ def test_periapsis_approaches_photon_sphere(ref):
         assert abs(tight.phi_end[0] - want) < 1e-13 / db
 
 
+def test_band_rays_within_the_conditioning_bound(ref):
+    """Rays in the critical band, 1e-3 M <= |b - b_c| <= 0.05 M, from cameras
+    at 10-100 M: the first integral drifts by at most 1e-10 relative along
+    each ray (rtol 1e-10), and the exit azimuth of the escaping ones matches
+    the quadrature within 1e-8 + b 1e-10 / (b - b_c).  That is the bound the
+    GPU parity tests apply to band rays: near b_c the sweep behaves like
+    -ln(b - b_c), so a drift D of E = 1/b^2 moves the end by about
+    b D / (2 (b - b_c)).  A controller that let the drift grow, or a wrong
+    coefficient that only shows near the photon sphere, fails here."""
+    rng = np.random.default_rng(31)
+    M = 1.0
+    rows = []
+    for _ in range(120):
+        delta = math.exp(rng.uniform(math.log(1e-3), math.log(0.05)))
+        if rng.uniform() < 0.3:
+            delta = -delta
+        b = Q.B_CRIT + delta
+        r0 = rng.uniform(10.0, 100.0)
+        sin_psi = (1.0 / r0) / math.sqrt(1.0 / b**2 + 2 * M / r0**3)
+        o, d = _plane_rays([r0], [math.pi - math.asin(sin_psi)])
+        out = ref.trace_rays(o, d, ref.scene(M))
+        rows.append((delta, r0, out))
+    for delta, r0, out in rows:
+        assert out.e_drift[0] <= 1e-10, (delta, out.e_drift[0])
+        if delta > 0:
+            assert out.cls[0] == ref.SKY
+            want = Q.exit_phi(M, out.b[0], r0, 1000.0, True)
+            bound = 1e-8 + out.b[0] * 1e-10 / (out.b[0] - Q.B_CRIT)
+            assert abs(out.phi_end[0] - want) <= bound, (delta, r0, out.phi_end[0] - want, bound)
+        else:
+            assert out.cls[0] == ref.CAPTURED
+
+
 def test_disk_hit_radius_matches_quadrature(ref):
     """Camera on the +z axis: every ray's orbital plane contains the z axis,
     so it meets the disk plane exactly at phi = pi/2.  The hit radius must be
