@@ -89,7 +89,38 @@ void timing_end(int slot, hipStream_t s) {
     (void)hipEventRecord(g_timed[slot].b, s);
 }
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Layout of the per-ray workspace for up to `cap` rays: rec, res, q64rec
+// (16 B per ray each), the surrogate list (qsurrec 16 B, qsur 4 B per entry,
+// kSurSlices * sur_slice_cap(cap) entries), u0 (8 B), clst and q64 (4 B
+// each), path (1 B), the queue counters and 4 path counters.  Returns the
+// bytes it needs; with base != NULL also points w and counts into it.
+constexpr size_t carve_workspace(char* base, int64_t cap, bh::Work* w,
+                                 unsigned long long** counts) {
+    const int64_t scap = bh::kSurSlices * bh::sur_slice_cap(cap);
+    const size_t sz16 = align256((size_t)cap * 16), sz8 = align256((size_t)cap * 8),
+                 sz4 = align256((size_t)cap * 4), sz1 = align256((size_t)cap);
+    const size_t szs16 = align256((size_t)scap * 16), szs4 = align256((size_t)scap * 4);
+    const size_t szc = align256(sizeof(int32_t) * bh::kCtrInts);
+    const size_t total = 3 * sz16 + szs16 + sz8 + 2 * sz4 + szs4 + sz1 + szc + 256;
+    if (base) {
+        char* c = base;
+        *w = bh::Work{};
+        w->rec = (double2*)c; c += sz16;
+        w->res = (double2*)c; c += sz16;
+        w->q64rec = (double2*)c; c += sz16;
+        w->qsurrec = (double2*)c; c += szs16;
+        w->qsur = (int32_t*)c; c += szs4;
+        w->u0 = (double*)c; c += sz8;
+        w->clst = (int32_t*)c; c += sz4;
+        w->q64 = (int32_t*)c; c += sz4;
+        w->path = (uint8_t*)c; c += sz1;
+        w->ctr = (int32_t*)c; c += szc;
+        *counts = (unsigned long long*)c;
+    }
+    return total;
+}
 
 bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
     int dev = 0;
@@ -106,14 +137,7 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
     }
     if (n > ws.cap || ws.base == nullptr) {
         int64_t cap = n > 4096 ? n : 4096;
-        // per ray: u0 (8 B), rec, res, q64rec (16 B each), clst, q64 (4 B each), path (1 B);
-        // the surrogate list (qsurrec 16 B, qsur 4 B) has kSurSlices * sur_slice_cap entries
-        const int64_t scap = bh::kSurSlices * bh::sur_slice_cap(cap);
-        const size_t sz16 = align256((size_t)cap * 16), sz8 = align256((size_t)cap * 8),
-                     sz4 = align256((size_t)cap * 4), sz1 = align256((size_t)cap);
-        const size_t szs16 = align256((size_t)scap * 16), szs4 = align256((size_t)scap * 4);
-        const size_t szc = align256(sizeof(int32_t) * bh::kCtrInts);
-        const size_t total = 3 * sz16 + szs16 + sz8 + 2 * sz4 + szs4 + sz1 + szc + 256;
+        const size_t total = carve_workspace(nullptr, cap, nullptr, nullptr);
         if (ws.base) {
             e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -129,18 +153,7 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
             (void)hipGetLastError();
             return fail(BH_ERR_NOMEM, "workspace of %zu bytes: %s", total, hipGetErrorString(e));
         }
-        char* c = (char*)p;
-        ws.w.rec = (double2*)c; c += sz16;
-        ws.w.res = (double2*)c; c += sz16;
-        ws.w.q64rec = (double2*)c; c += sz16;
-        ws.w.qsurrec = (double2*)c; c += szs16;
-        ws.w.qsur = (int32_t*)c; c += szs4;
-        ws.w.u0 = (double*)c; c += sz8;
-        ws.w.clst = (int32_t*)c; c += sz4;
-        ws.w.q64 = (int32_t*)c; c += sz4;
-        ws.w.path = (uint8_t*)c; c += sz1;
-        ws.w.ctr = (int32_t*)c; c += szc;
-        ws.counts = (unsigned long long*)c;
+        carve_workspace((char*)p, cap, &ws.w, &ws.counts);
         ws.base = p;
         ws.cap = cap;
     }
@@ -328,13 +341,12 @@ bh::DevCam make_cam(const bh_camera* cam) {
     return c;
 }
 
-// The shared sequence: reset counters, set-up, integrate, shade.
-bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const bh_scene* scene,
-              const bh_options* opt, float* rgba, const bh_ray_out* out, hipStream_t stream,
-              int samples_side = 1) {
-    Workspace* ws = nullptr;
-    bh_status st = get_workspace(src.n, stream, &ws);
-    if (st != BH_OK) return st;
+// The shared sequence on a given workspace w (capacity >= src.n rays):
+// reset counters, set-up, integrate, shade.  timed: bracket the launches with
+// the bh_timing events (when enabled).
+bh_status run_on(const bh::Work& ws_w, int cus, const bh::Source& src, bool explicit_u0,
+                 double u0_uniform, const bh_scene* scene, const bh_options* opt, float* rgba,
+                 const bh_ray_out* out, hipStream_t stream, int samples_side, bool timed) {
     const bh::DevScene sc = dev_scene(scene);
     const bh::DevTol tol = dev_tol(opt, scene);
     bh::DevRoute rt = dev_route(opt, scene);
@@ -347,37 +359,72 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
         rt.r0m = (float)(1.0 / (u0_uniform * scene->M));
         sur_pack = rt.trust ? bh::surrogate_pack(opt->surrogate) : nullptr;
     }
-    bh::Work w = ws->w;
+    bh::Work w = ws_w;
     if (!explicit_u0) w.u0 = nullptr;
     hipError_t e = bh::launch_reset(w.ctr, stream);
     if (e != hipSuccess) return hip_fail(e, "reset");
-    int t = timing_begin(0, stream);
+    int t = timed ? timing_begin(0, stream) : -1;
     e = bh::launch_setup(src, sc, rt, w, out ? out->b : nullptr, stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "setup");
     if (sur_pack) {
-        t = timing_begin(3, stream);
-        e = bh::launch_surrogate_render(src.n, w, sur_pack, scene->M, 1.0 / u0_uniform, ws->cus,
-                                        stream);
+        t = timed ? timing_begin(3, stream) : -1;
+        e = bh::launch_surrogate_render(src.n, w, sur_pack, scene->M, 1.0 / u0_uniform, cus, stream);
         timing_end(t, stream);
         if (e != hipSuccess) return hip_fail(e, "surrogate");
     }
-    t = timing_begin(1, stream);
+    t = timed ? timing_begin(1, stream) : -1;
     e = opt->fixed_eps > 0.0
             ? bh::launch_integrate_paper(src.n, explicit_u0, u0_uniform, sc, tol, opt->fixed_eps, w,
-                                         ws->cus, stream)
+                                         cus, stream)
             : bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w,
-                                   ws->cus, opt->grid_blocks, auto_chunk(opt), stream);
+                                   cus, opt->grid_blocks, auto_chunk(opt), stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "integrate");
-    t = timing_begin(2, stream);
+    t = timed ? timing_begin(2, stream) : -1;
     e = samples_side > 1
             ? bh::launch_shade_samples(src, sc, w, rgba, dev_out(out), opt->precision, samples_side,
                                        stream)
             : bh::launch_shade(src, sc, w, rgba, dev_out(out), opt->precision, stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "shade");
-    ws->last_n = src.n;
+    return BH_OK;
+}
+
+// The same sequence on the library's per-device workspace (grown on demand).
+bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const bh_scene* scene,
+              const bh_options* opt, float* rgba, const bh_ray_out* out, hipStream_t stream,
+              int samples_side = 1) {
+    Workspace* ws = nullptr;
+    bh_status st = get_workspace(src.n, stream, &ws);
+    if (st != BH_OK) return st;
+    st = run_on(ws->w, ws->cus, src, explicit_u0, u0_uniform, scene, opt, rgba, out, stream,
+                samples_side, true);
+    if (st == BH_OK) ws->last_n = src.n;
+    return st;
+}
+
+// Checks of bh_render's arguments; fills the ray source (the sample camera
+// for samples_side > 1) and the sample count per side.
+bh_status render_source(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
+                        const float* rgba, bh::Source* src, int* nside) {
+    bh_status st = check_scene(scene);
+    if (st != BH_OK) return st;
+    if ((st = check_opt(opt)) != BH_OK) return st;
+    if ((st = check_camera(cam, scene)) != BH_OK) return st;
+    if (!rgba) return fail(BH_ERR_ARG, "rgba is NULL");
+    const int n = opt->samples_side > 1 ? opt->samples_side : 1;
+    // n x n samples per pixel: the rays of the same camera at n times the
+    // resolution (their pixel centres are the stratified sub-pixel centres)
+    bh_camera sub = *cam;
+    if ((int64_t)cam->width * n * cam->height * n > INT32_MAX)
+        return fail(BH_ERR_ARG, "image * samples must have < 2^31 rays");
+    sub.width = cam->width * n;
+    sub.height = cam->height * n;
+    *src = bh::Source{};
+    src->n = (int64_t)sub.width * sub.height;
+    src->cam = make_cam(&sub);
+    *nside = n;
     return BH_OK;
 }
 
@@ -425,22 +472,10 @@ bh_status bh_trace_rays(const double* origin, const double* dir, int64_t n, cons
 
 bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
                     float* rgba, const bh_ray_out* per_pixel, void* stream) {
-    bh_status st = check_scene(scene);
+    bh::Source src;
+    int n = 1;
+    bh_status st = render_source(cam, scene, opt, rgba, &src, &n);
     if (st != BH_OK) return st;
-    if ((st = check_opt(opt)) != BH_OK) return st;
-    if ((st = check_camera(cam, scene)) != BH_OK) return st;
-    if (!rgba) return fail(BH_ERR_ARG, "rgba is NULL");
-    const int n = opt->samples_side > 1 ? opt->samples_side : 1;
-    // n x n samples per pixel: the rays of the same camera at n times the
-    // resolution (their pixel centres are the stratified sub-pixel centres)
-    bh_camera sub = *cam;
-    if ((int64_t)cam->width * n * cam->height * n > INT32_MAX)
-        return fail(BH_ERR_ARG, "image * samples must have < 2^31 rays");
-    sub.width = cam->width * n;
-    sub.height = cam->height * n;
-    bh::Source src{};
-    src.n = (int64_t)sub.width * sub.height;
-    src.cam = make_cam(&sub);
     return run(src, false, 1.0 / cam->r, scene, opt, rgba, per_pixel, (hipStream_t)stream, n);
 }
 

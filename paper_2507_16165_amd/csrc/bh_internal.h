@@ -130,7 +130,7 @@ constexpr int kCtrInts = kCtrSur + kSurSlices * kCtrStride;
 // its slice's counter); a slice holds at most the rays of its blocks.
 // Capacity of one slice for n rays (the list needs kSurSlices times this, at
 // most n + kSurSlices * kBlock entries).
-__host__ __device__ inline int64_t sur_slice_cap(int64_t n) {
+__host__ __device__ constexpr int64_t sur_slice_cap(int64_t n) {
     const int64_t blocks = (n + kBlock - 1) / kBlock;
     return (blocks + kSurSlices - 1) / kSurSlices * kBlock;
 }
