@@ -175,6 +175,23 @@ bh_status bh_trace_rays(const double* origin, const double* dir, int64_t n,
 bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
                     float* rgba, const bh_ray_out* per_pixel, void* stream);
 
+/* bh_render for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, checks, kernels and results as bh_render (the image and records
+ * are bit-identical); it calls no hipMalloc, hipFree or other allocating
+ * routine.  Its per-ray workspace is a fixed array in the library's device
+ * memory, sized for BH_NOALLOC_MAX_RAYS rays (about 89 MB; rays = width *
+ * height * samples_side^2).  Each GPU holds its own copy from the library's
+ * first use on it until the process ends.  Larger frames return BH_ERR_ARG
+ * with nothing enqueued.  Every call on one GPU shares that GPU's array and
+ * it keeps the last call's contents (each call clears what must start at
+ * zero itself): calls that overlap on one GPU (several streams or threads)
+ * race, so order them on one stream.  It does not share memory with
+ * bh_render's workspace, and bh_last_counts does not report it. */
+#define BH_NOALLOC_MAX_RAYS 1048576
+bh_status bh_render_noalloc(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
+                            float* rgba, const bh_ray_out* per_pixel, void* stream);
+
 /* Sizes the workspace of the current device for frames of up to n rays
  * (synchronises the device if it grows). */
 bh_status bh_reserve(int64_t n);

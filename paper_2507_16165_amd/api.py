@@ -86,6 +86,8 @@ def lib():
     L.bh_render.argtypes = [C.POINTER(Camera), C.POINTER(Scene), C.POINTER(Options), C.c_void_p,
                             C.POINTER(RayOut), C.c_void_p]
     L.bh_render.restype = st
+    L.bh_render_noalloc.argtypes = L.bh_render.argtypes
+    L.bh_render_noalloc.restype = st
     L.bh_reserve.argtypes = [C.c_int64]
     L.bh_reserve.restype = st
     L.bh_last_counts.argtypes = [C.POINTER(C.c_int64), C.c_void_p]
@@ -232,6 +234,31 @@ def render(camera: inputs.Camera, scene: inputs.Scene, opt: Options | None = Non
     check(lib().bh_render(C.byref(cam), C.byref(sc), C.byref(opt), rgba.data_ptr(),
                           C.byref(ro) if ro is not None else None, _stream(stream)))
     return rgba, out
+
+
+NOALLOC_MAX_RAYS = 1048576   # BH_NOALLOC_MAX_RAYS
+
+
+def render_noalloc(camera: inputs.Camera, scene: inputs.Scene, rgba, opt: Options | None = None,
+                   out=None, stream=None) -> None:
+    """bh_render_noalloc: renders into the caller's ``rgba`` (H, W, 4) float32
+    tensor and, if given, the per-pixel tensors of ``out`` (a dict as
+    ``alloc_out`` returns); the library allocates nothing for the call."""
+    H, W = camera.height, camera.width
+    assert rgba.dtype.itemsize == 4 and rgba.is_contiguous() and rgba.numel() == H * W * 4
+    ro = None
+    if out is not None:
+        ro = RayOut(*[out[f].data_ptr() if f in out else None for f in ALL_FIELDS])
+    opt = opt or options()
+    cam = camera_struct(camera)
+    sc = scene_struct(scene)
+    check(lib().bh_render_noalloc(C.byref(cam), C.byref(sc), C.byref(opt), rgba.data_ptr(),
+                                  C.byref(ro) if ro is not None else None, _stream(stream)))
+
+
+def alloc_out(n: int, fields=ALL_FIELDS, device="cuda") -> dict:
+    """Per-ray output tensors of length n (caller-owned), keyed by field."""
+    return _alloc_out(n, fields, device)[0]
 
 
 def reserve(n: int) -> None:

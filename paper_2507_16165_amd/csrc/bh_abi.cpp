@@ -404,6 +404,55 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     return st;
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Allocation-free rendering (bh_render_noalloc).  The per-ray workspace of a
+// call is this fixed device array, laid out exactly as the per-device
+// workspace for BH_NOALLOC_MAX_RAYS rays.  Each GPU the library runs on holds
+// its own copy at its own address from the code object's load until the
+// process ends.  Host code must not pass the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returned on that device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocBytes = carve_workspace(nullptr, BH_NOALLOC_MAX_RAYS, nullptr, nullptr);
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_nmu;
+char* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+int g_scratch_cus[kMaxDevices] = {};
+
+// Device address of this device's `scratch` array (looked up once per device,
+// with that device current) and the device's CU count.  No allocation.
+bh_status noalloc_scratch(char** base, int* cus) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(BH_ERR_UNSUPPORTED, "bh_render_noalloc supports devices 0..%d", kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_nmu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(BH_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        int c = 0;
+        e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        g_scratch_cus[dev] = c > 0 ? c : 256;
+        g_scratch_dev[dev] = (char*)p;
+    }
+    *base = g_scratch_dev[dev];
+    *cus = g_scratch_cus[dev];
+    return BH_OK;
+}
+
 // Checks of bh_render's arguments; fills the ray source (the sample camera
 // for samples_side > 1) and the sample count per side.
 bh_status render_source(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
@@ -477,6 +526,30 @@ bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_option
     bh_status st = render_source(cam, scene, opt, rgba, &src, &n);
     if (st != BH_OK) return st;
     return run(src, false, 1.0 / cam->r, scene, opt, rgba, per_pixel, (hipStream_t)stream, n);
+}
+
+bh_status bh_render_noalloc(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
+                            float* rgba, const bh_ray_out* per_pixel, void* stream) {
+    bh::Source src;
+    int n = 1;
+    bh_status st = render_source(cam, scene, opt, rgba, &src, &n);
+    if (st != BH_OK) return st;
+    if (src.n > BH_NOALLOC_MAX_RAYS)
+        return fail(BH_ERR_ARG,
+                    "bh_render_noalloc: %lld rays (width * height * samples_side^2) exceed its "
+                    "fixed workspace of %d rays",
+                    (long long)src.n, BH_NOALLOC_MAX_RAYS);
+    char* base = nullptr;
+    int cus = 0;
+    if ((st = noalloc_scratch(&base, &cus)) != BH_OK) return st;
+    bh::Work w{};
+    unsigned long long* counts = nullptr;
+    carve_workspace(base, BH_NOALLOC_MAX_RAYS, &w, &counts);
+    // Same launch sequence and kernels as bh_render; no timing events (their
+    // creation could allocate).  The sequence starts by clearing the queue
+    // counters with a kernel, so nothing left by an earlier call is read.
+    return run_on(w, cus, src, false, 1.0 / cam->r, scene, opt, rgba, per_pixel,
+                  (hipStream_t)stream, n, false);
 }
 
 bh_status bh_reserve(int64_t n) {

@@ -172,3 +172,26 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
         py = structs[cname]
         want = C.sizeof(py) if field == "size" else getattr(py, field).offset
         assert int(val) == want, (cname, field, int(val), want)
+
+
+def test_render_noalloc_rejects_frames_beyond_its_workspace():
+    """bh_render_noalloc has a fixed workspace of BH_NOALLOC_MAX_RAYS rays:
+    larger frames (samples included) are refused before any device call,
+    with the same argument checks as bh_render first."""
+    L = api.lib()
+    sc = api.scene_struct(inputs.Scene(M=1.0))
+
+    def call(cam, opt=None, rgba=1):
+        c = api.camera_struct(cam)
+        o = opt or api.options()
+        return L.bh_render_noalloc(C.byref(c), C.byref(sc), C.byref(o), C.c_void_p(rgba), None, None)
+
+    assert api.NOALLOC_MAX_RAYS == 1 << 20
+    assert call(inputs.Camera(30, 90, 0, 60, 1025, 1024)) == api.BH_ERR_ARG
+    assert "fixed workspace" in L.bh_last_error().decode()
+    assert call(inputs.Camera(30, 90, 0, 60, 512, 512), api.options(samples_side=3)) == api.BH_ERR_ARG
+    assert "fixed workspace" in L.bh_last_error().decode()
+    assert call(inputs.Camera(2.5, 90, 0, 60, 8, 8)) == api.BH_ERR_ARG
+    assert "photon sphere" in L.bh_last_error().decode()
+    assert call(inputs.Camera(30, 90, 0, 60, 8, 8), rgba=0) == api.BH_ERR_ARG
+    assert L.bh_render_noalloc(None, None, None, None, None, None) == api.BH_ERR_ARG
