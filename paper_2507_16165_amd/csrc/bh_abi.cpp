@@ -300,8 +300,9 @@ bh_status check_camera(const bh_camera* cam, const bh_scene* scene) {
 }
 
 // Camera basis (per frame): position r (sin i cos a, sin i sin a, cos i),
-// forward = -position/r, up = -e_theta, right = forward x up.
-bh::DevCam make_cam(const bh_camera* cam) {
+// forward = -position/r, up = -e_theta, right = forward x up; and the FP32
+// routing thresholds of its rays in the scene.
+bh::DevCam make_cam(const bh_camera* cam, const bh_scene* scene, const bh_options* opt) {
     const double inc = cam->incl_deg * kPi / 180.0, az = cam->azim_deg * kPi / 180.0;
     const double ph[3] = {sin(inc) * cos(az), sin(inc) * sin(az), cos(inc)};
     bh::DevCam c{};
@@ -338,6 +339,17 @@ bh::DevCam make_cam(const bh_camera* cam) {
     c.f_ax = (float)c.ax;
     c.f_bx = (float)c.bx;
     c.f_tan_half = (float)c.tan_half;
+    // E = 1/b^2 is decreasing in b: b above the band is E < 1/(b_c + band)^2,
+    // b below it E > 1/(b_c - band)^2.  E in FP32 is good to about 1e-6
+    // relative (a few roundings of positive terms); the thresholds move by
+    // 1e-5, so a ray the FP32 test calls clear is clear in FP64 too.
+    constexpr double kMargin = 1e-5;
+    const double M = scene->M, bc = 3.0 * sqrt(3.0) * M, band = opt->band_halfwidth * M;
+    c.f_u0 = (float)c.u0;
+    c.f_c0 = (float)(c.u0 * c.u0 * (1.0 - 2.0 * M * c.u0));
+    const double b_hi = bc + band, b_lo = bc - band;
+    c.f_e_in = b_hi > 0.0 ? (float)((1.0 - kMargin) / (b_hi * b_hi)) : __builtin_inff();
+    c.f_e_out = b_lo > 0.0 ? (float)((1.0 + kMargin) / (b_lo * b_lo)) : __builtin_inff();
     return c;
 }
 
@@ -472,7 +484,7 @@ bh_status render_source(const bh_camera* cam, const bh_scene* scene, const bh_op
     sub.height = cam->height * n;
     *src = bh::Source{};
     src->n = (int64_t)sub.width * sub.height;
-    src->cam = make_cam(&sub);
+    src->cam = make_cam(&sub, scene, opt);
     *nside = n;
     return BH_OK;
 }
@@ -662,7 +674,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         if ((st = check_camera(&q.cam, &q.scene)) != BH_OK)
             return fail(st, "request %d: %s", r, bh_last_error());
         if (!q.rgba) return fail(BH_ERR_ARG, "request %d: rgba is NULL", r);
-        req[r].cam = make_cam(&q.cam);
+        req[r].cam = make_cam(&q.cam, &q.scene, opt);
         req[r].sc = dev_scene(&q.scene);
         req[r].rt = dev_route(opt, &q.scene);
         req[r].rgba = q.rgba;

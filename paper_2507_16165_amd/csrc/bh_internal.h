@@ -81,6 +81,12 @@ struct DevCam {
     // FP32 copies (rounded once on the host) for the FP32 shading path.
     float f_right[3], f_up[3], f_e1[3];
     float f_ax, f_bx, f_tan_half;
+    // FP32 set-up of FP32-mode renders: u0 and u0^2 - 2 M u0^3 in float, and
+    // the critical band's edges as thresholds on E = w0^2 + u0^2 - 2 M u0^3
+    // = 1/b^2, each moved away from the band by a relative margin far above
+    // the error of E computed in FP32: E < f_e_in is clearly above the band,
+    // E > f_e_out clearly below it (+inf: nothing is).
+    float f_u0, f_c0, f_e_in, f_e_out;
     int W, H;
 };
 

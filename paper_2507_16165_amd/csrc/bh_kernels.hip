@@ -255,6 +255,69 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
     return to;
 }
 
+// Set-up of camera pixel i (workspace index g) in FP32 mode without surrogate
+// routing.  The routing needs the impact parameter to FP64 accuracy only
+// near a band edge: E = w0^2 + u0^2 - 2 M u0^3 = 1/b^2 is first formed in
+// FP32 from the start slope, and a ray whose E is clearly outside the band
+// (thresholds moved 1e-5 relative away from it, DevCam) is routed on that
+// value -- to the FP32 integrator, or, below the band in a scene without a
+// disk, to analytic capture: the decisions the FP64 values would take.  Every
+// other ray (in or near the band, or the radial ray through the image
+// centre) takes the FP64 set-up.
+//
+// The start slope w0 = u0 / sqrt(x^2 + y^2) is the FP32 integrator's input
+// rounded once to float, as the FP64 set-up rounds it: x, y and x^2 + y^2 in
+// FP64 (in FP32 the image-plane coordinates cancel near the image centre,
+// and a start-direction error is amplified like 1/|b - b_c| by the sweep),
+// the reciprocal square root from the hardware estimate and one Newton step
+// (relative error ~1e-14, far below float rounding).  out_b (single renders
+// only) is the FP64 b.
+template <bool BATCH, bool R32>
+__device__ __forceinline__ int setup_camera32(const DevCam& cam, const DevScene& sc,
+                                              const DevRoute& rt, int64_t i, int64_t g,
+                                              const Work& w, double* out_b, double& b,
+                                              double& w0, double& phi1) {
+    double pxd, pyd;
+    pixel_of(cam, i, pxd, pyd);
+    const double x = fma(pxd + 0.5, cam.ax, cam.bx);
+    const double y = fma(-(pyd + 0.5), cam.ax, cam.tan_half);
+    const double s2 = fma(x, x, y * y);
+    double iv = __builtin_amdgcn_rsq(s2);
+    iv = fma(0.5 * iv, fma(-s2 * iv, iv, 1.0), iv);
+    const double w0d = cam.u0 * iv;
+    const float w0f = (float)w0d;
+    const float E = fmaf(w0f, w0f, cam.f_c0);
+    const bool above = E < cam.f_e_in, below = E > cam.f_e_out;
+    if (!(s2 > 1e-30 && s2 < 1e30) || !(above | below))
+        return setup_ray<BATCH, R32>(camera_basis(cam, i, sc.M, sc.r_sky), sc, rt, g, w, out_b, b,
+                                     w0, phi1);
+    b = 0.0;
+    if (out_b) out_b[g] = rsqrt_d(fma(w0d, w0d, cam.u0 * cam.u0 * (1.0 - 2.0 * sc.M * cam.u0)));
+    if (below & (rt.analytic_capture != 0) & !sc.has_disk) {
+        // below the potential peak: falls in, no disk to hit
+        if (!BATCH) w.path[g] = PATH_NONE;
+        if (R32) {
+            w.rec32[g] = make_float2(__builtin_nanf(""), 0.0f);
+            w.res32[g] = make_float2(0.0f, 0.0f);
+        } else {
+            w.rec[g] = make_double2(nan_d(), 0.0);
+            w.res[g] = make_double2(0.0, 0.0);
+        }
+        w.clst[g] = CAPTURED;
+        w0 = 0.0;
+        phi1 = 0.0;
+        return kToNone;
+    }
+    // first disk-plane crossing (e2 = (x right + y up) / sqrt(x^2 + y^2))
+    phi1 = sc.has_disk ? first_crossing32(cam.e1[2], fma(x, cam.right[2], y * cam.up[2]) * iv)
+                       : __builtin_inf();
+    if (!BATCH) w.path[g] = PATH_FP32;
+    if (R32) w.rec32[g] = make_float2(w0f, (float)phi1);
+    else w.rec[g] = make_double2((double)w0f, phi1);
+    w0 = (double)w0f;
+    return kToNone;
+}
+
 // Wave-aggregated append to the FP64 band queue: one atomic per wavefront
 // that holds band rays (a fraction of a percent of all wavefronts).
 __device__ __forceinline__ void append_band(bool to_q64, int64_t i, double w0, double phi1,
@@ -308,7 +371,12 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int to = kToNone;
     double b = 0.0, w0 = 0.0, phi1 = 0.0;
-    if (i < src.n) to = setup_ray(source_basis(src, i, sc.M, sc.r_sky), sc, rt, i, w, out_b, b, w0, phi1);
+    if (i < src.n) {
+        if (!src.origin && rt.precision == 1 && !rt.trust)
+            to = setup_camera32<false, false>(src.cam, sc, rt, i, i, w, out_b, b, w0, phi1);
+        else
+            to = setup_ray(source_basis(src, i, sc.M, sc.r_sky), sc, rt, i, w, out_b, b, w0, phi1);
+    }
     append_band(to == kToBand, i, w0, phi1, w);
     if (rt.trust) append_sur(to == kToSur, i, b, w0, src.n, w);
 }
@@ -345,6 +413,17 @@ __device__ __forceinline__ S uniform_load(const S* __restrict__ p) {
     return out;
 }
 
+// Set-up of pixel i of request q (workspace index g) in a batch: FP32-mode
+// requests take the FP32 camera set-up, FP64-mode ones the FP64 set-up.
+template <bool R32>
+__device__ __forceinline__ int batch_ray(const ReqDev& q, int64_t i, int64_t g, const Work& w,
+                                         double& b, double& w0, double& phi1) {
+    if (q.rt.precision == 1)
+        return setup_camera32<true, R32>(q.cam, q.sc, q.rt, i, g, w, nullptr, b, w0, phi1);
+    return setup_ray<true, R32>(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
+                                nullptr, b, w0, phi1);
+}
+
 // Batch set-up: all requests' rays in one index space; each ray also records
 // its request for the integrator.  A block whose rays lie in one request (all
 // but a few) takes that request's constants as uniform values; a block that
@@ -363,15 +442,13 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
         const ReqDev q = uniform_load(b.req + r0);
         if (g < b.total) {
             w.rq[g] = r0;
-            to = setup_ray<true, R32>(camera_basis(q.cam, g - s_off[r0], q.sc.M, q.sc.r_sky), q.sc, q.rt, g,
-                           w, nullptr, bi, w0, phi1);  // no surrogate routing
+            to = batch_ray<R32>(q, g - s_off[r0], g, w, bi, w0, phi1);  // no surrogate routing
         }
     } else if (g < b.total) {
         const int r = find_req(s_off, b.nreq, g);
         const ReqDev& q = b.req[r];
         w.rq[g] = r;
-        to = setup_ray<true, R32>(camera_basis(q.cam, g - s_off[r], q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
-                       nullptr, bi, w0, phi1);
+        to = batch_ray<R32>(q, g - s_off[r], g, w, bi, w0, phi1);
     }
     append_band(to == kToBand, g, w0, phi1, w);
 }
