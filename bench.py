@@ -116,6 +116,8 @@ def main() -> int:
                     help="skip the surrogate leg (training and the surrogate render)")
     ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving leg")
+    ap.add_argument("--no-sky-images", action="store_true",
+                    help="skip the sky-image size sweep")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the fixed-step (paper) mode sweep")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -206,14 +208,37 @@ def main() -> int:
     # schedule (the batch's pixels equal the per-frame renders), so one
     # instrumented per-frame pass gives the count of the timed launches.
     def step_evals(opt):
+        """Summed step evaluations and rays per path over the frames, and the
+        controller's split (accepted, rejected, Newton re-steps per path)
+        from the instrumented integrator (bh_last_stats)."""
         tot = 0
         per_path = {}
+        split = {}
+        opt_s = api.options(precision=opt.precision, rtol=opt.rtol, rtol_fp32=opt.rtol_fp32,
+                            collect_stats=1)
         for f, buf in zip(frames, bufs):
-            _, out = api.render(f.camera, f.scene, opt, rgba=buf, fields=("steps", "path"))
+            _, out = api.render(f.camera, f.scene, opt_s, rgba=buf, fields=("steps", "path"))
             tot += int(out["steps"].to(torch.int64).sum().item())
             for p in (api.PATH_NONE, api.PATH_FP64, api.PATH_FP32):
                 per_path[p] = per_path.get(p, 0) + int((out["path"] == p).sum().item())
-        return tot, per_path
+            st = api.last_stats()
+            assert st["step_evals"] == int(out["steps"].to(torch.int64).sum().item())
+            for k in ("accepted", "rejected", "newton", "capped"):
+                for q in ("fp64", "fp32"):
+                    split[(k, q)] = split.get((k, q), 0) + st[k][q]
+        return tot, per_path, split
+
+    def controller(split, per_path):
+        """Per integrated ray of each path: accepted steps, rejected trial
+        steps and Newton re-steps of the sky crossing."""
+        out = {}
+        for q, p in (("fp32", api.PATH_FP32), ("fp64", api.PATH_FP64)):
+            n = max(1, per_path.get(p, 0))
+            out[q] = {k + "_per_ray": round(split[(k, q)] / n, 3)
+                      for k in ("accepted", "rejected", "newton")}
+            out[q]["rays"] = per_path.get(p, 0)
+            out[q]["capped"] = split[("capped", q)]
+        return out
 
     def roof(evals, t, k):
         """(FLOP per integrator launch, mean launch ms, TFLOP/s) of k timed steps."""
@@ -221,11 +246,11 @@ def main() -> int:
         flop = evals * FLOP_PER_STEP / (n / k)
         return flop, ms / n, flop / (ms / n * 1e-3) / 1e12
 
-    evals, paths = step_evals(opt_fast)
+    evals, paths, split = step_evals(opt_fast)
     flop_launch, avg_launch_ms, achieved = roof(evals, tim, args.steps)
     _, avg_launch_frames, achieved_frames = roof(evals, tim_frames, args.steps)
     if tim64 is not None:
-        evals64, _ = step_evals(opt_fp64)
+        evals64, paths64, split64 = step_evals(opt_fp64)
         _, _, achieved64 = roof(evals64, tim64, args.fp64_steps)
     else:
         evals64, achieved64 = float("nan"), float("nan")
@@ -267,12 +292,15 @@ def main() -> int:
                        "ms_per_step": round(ms_step64, 4), "rtol": opt_fp64.rtol,
                        "achieved_tflops": round(achieved64, 3),
                        "frac": round(achieved64 / PEAK_FP64_TFLOPS, 4),
-                       "step_evals_per_ray": round(evals64 / rays_per_step, 3)},
+                       "step_evals_per_ray": round(evals64 / rays_per_step, 3),
+                       "controller": (controller(split64, paths64)["fp64"]
+                                      if tim64 is not None else None)},
         "speedup_vs_fp64": round(value / value64, 3),
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
         "paths": {"setup_only": paths.get(0, 0), "fp64_band": paths.get(1, 0),
                   "fp32": paths.get(2, 0)},
         "step_evals_per_ray": round(evals / rays_per_step, 3),
+        "controller": controller(split, paths),
         "roofline": {
             "kernel": ROOFLINE_KERNEL,
             "bound": "alu",
@@ -311,6 +339,8 @@ def main() -> int:
         if sweep is not None:
             line["paper_mode_sweep"]["adaptive_fp32_band_surrogate"] = line["surrogate"].pop("sweep_point")
     
+    if not args.no_sky_images:
+        line["sky_image_sweep"] = sky_image_leg(frames, bufs, api, torch, opt_fast)
     if not args.no_batch:
         line["batch_serving"] = batch_leg(args, api, torch)
     if not args.no_cpu_baseline:
@@ -581,6 +611,51 @@ def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None):
     if point is not None:
         res["sweep_point"] = point
     return res
+
+
+def sky_image_leg(frames, bufs, api, torch, opt, reps=3):
+    """The background-image size axis: the step's frames as one batch with the
+    procedural checker sky and with equirectangular sky images of growing
+    size (seeded random texels generated on the device; the timing does not
+    depend on their values).  Each sky ray reads its four bilinear taps from
+    the image during shading; reported per size: the step time and the
+    shading time per frame."""
+    from dataclasses import replace
+
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    rays = sum(f.camera.width * f.camera.height for f in frames)
+    out = {}
+    for size in (None, (1024, 512), (4096, 2048), (16384, 8192)):
+        tex = None
+        if size is None:
+            name, fr = "checker", frames
+        else:
+            tw, th = size
+            tex = torch.rand((th, tw, 4), generator=gen, device="cuda", dtype=torch.float32)
+            tex[..., 3] = 1.0
+            name = f"{tw}x{th}"
+            fr = [replace(f, scene=replace(f.scene, sky_tex=tex)) for f in frames]
+        b = api.Batch(fr, opt, use_graph=False, images=bufs)
+        b.launch()
+        torch.cuda.synchronize()
+        api.timing_enable(True)
+        api.timing_read()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        tim = api.timing_read()
+        api.timing_enable(False)
+        b.close()
+        out[name] = {"texture_mb": round(0.0 if tex is None else tex.numel() * 4 / 1e6, 1),
+                     "ms_per_step": round(ms, 4),
+                     "mrays_per_s": round(rays / (ms * 1e-3) / 1e6, 1),
+                     "shade_ms_per_frame": round(tim["shade"][0] / reps / len(frames), 4)}
+        log(f"sky images: {name}: {ms:.3f} ms/step")
+        del tex
+    return out
 
 
 def batch_leg(args, api, torch):

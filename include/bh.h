@@ -132,6 +132,9 @@ typedef struct {
                                 results; it only changes the schedule                 */
     int    refill_fp64;      /* the same for the FP64 rays of FP64 mode; 0 = auto (6).
                                 (The critical band of FP32 mode always refills at 1.) */
+    int    collect_stats;    /* bh_render / bh_trace_rays: 1 = count the statistics that
+                                bh_last_stats reports, with an instrumented integrator (the
+                                same results, somewhat slower); 0 = off.  Batches: must be 0 */
 } bh_options;
 
 /* Optional per-ray outputs (device arrays of length n, any may be NULL).
@@ -187,7 +190,8 @@ bh_status bh_render(const bh_camera* cam, const bh_scene* scene, const bh_option
  * it keeps the last call's contents (each call clears what must start at
  * zero itself): calls that overlap on one GPU (several streams or threads)
  * race, so order them on one stream.  It does not share memory with
- * bh_render's workspace, and bh_last_counts does not report it. */
+ * bh_render's workspace, bh_last_counts does not report it, and
+ * collect_stats = 1 is BH_ERR_UNSUPPORTED. */
 #define BH_NOALLOC_MAX_RAYS 1048576
 bh_status bh_render_noalloc(const bh_camera* cam, const bh_scene* scene, const bh_options* opt,
                             float* rgba, const bh_ray_out* per_pixel, void* stream);
@@ -200,6 +204,31 @@ bh_status bh_reserve(int64_t n);
  * counts[0..3] = {set-up only, FP64 integrator, FP32 integrator, surrogate}.
  * Synchronises `stream`. */
 bh_status bh_last_counts(int64_t counts[4], void* stream);
+
+/* Statistics of the last bh_render / bh_trace_rays on this device that ran
+ * with bh_options.collect_stats = 1.  Steps are Dormand-Prince step
+ * evaluations (the per-ray count bh_ray_out.steps reports is accepted +
+ * rejected + newton of that ray). */
+typedef struct {
+    int64_t rays;            /* rays of the call (every sample of every pixel)          */
+    int64_t cls[5];          /* rays per end class, BH_SKY .. BH_INVALID                */
+    int64_t path[4];         /* rays per BH_PATH_*                                      */
+    int64_t step_evals;      /* all step evaluations of the call                       */
+    int64_t accepted[2];     /* accepted steps: [0] FP64 integrator (FP64 mode, or the
+                                critical band of FP32 mode), [1] FP32 integrator        */
+    int64_t rejected[2];     /* rejected trial steps                                    */
+    int64_t newton[2];       /* re-steps of the sky crossing's Newton refinement        */
+    int64_t capped[2];       /* rays ended by the step or sweep cap (BH_UNRESOLVED)     */
+    int64_t sur_listed;      /* rays routed to the surrogate at set-up                  */
+    int64_t sur_fallback;    /* of those, rays the network handed back to the FP32
+                                integrator (capture logit not negative)                 */
+    int64_t sur_untrusted;   /* rays eligible for the surrogate whose trust-map bin is
+                                not trusted (they stay on the integrator)              */
+} bh_stats;
+
+/* Copies the statistics of the last call on this device into *st and
+ * synchronises `stream`.  BH_ERR_STATE if that call did not collect them. */
+bh_status bh_last_stats(bh_stats* st, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched rendering for serving: many requests (each a camera, a scene and an

@@ -43,7 +43,16 @@ class Options(C.Structure):
                 ("hmax", C.c_double), ("max_phi", C.c_double), ("max_steps", C.c_int),
                 ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
                 ("samples_side", C.c_int), ("batch_groups", C.c_int), ("fixed_eps", C.c_double),
-                ("surrogate", C.c_void_p), ("refill_fp32", C.c_int), ("refill_fp64", C.c_int)]
+                ("surrogate", C.c_void_p), ("refill_fp32", C.c_int), ("refill_fp64", C.c_int),
+                ("collect_stats", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("rays", C.c_int64), ("cls", C.c_int64 * 5), ("path", C.c_int64 * 4),
+                ("step_evals", C.c_int64), ("accepted", C.c_int64 * 2),
+                ("rejected", C.c_int64 * 2), ("newton", C.c_int64 * 2),
+                ("capped", C.c_int64 * 2), ("sur_listed", C.c_int64),
+                ("sur_fallback", C.c_int64), ("sur_untrusted", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -92,6 +101,8 @@ def lib():
     L.bh_reserve.restype = st
     L.bh_last_counts.argtypes = [C.POINTER(C.c_int64), C.c_void_p]
     L.bh_last_counts.restype = st
+    L.bh_last_stats.argtypes = [C.POINTER(Stats), C.c_void_p]
+    L.bh_last_stats.restype = st
     L.bh_timing_enable.argtypes = [C.c_int]
     L.bh_timing_enable.restype = st
     L.bh_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -269,6 +280,20 @@ def last_counts(stream=None) -> dict:
     arr = (C.c_int64 * 4)()
     check(lib().bh_last_counts(arr, _stream(stream)))
     return {"setup": arr[0], "fp64": arr[1], "fp32": arr[2], "surrogate": arr[3]}
+
+
+def last_stats(stream=None) -> dict:
+    """bh_last_stats of the last render/trace (which must have run with
+    collect_stats=1), as a dict; the FP64/FP32 pairs as {'fp64': .., 'fp32': ..}."""
+    s = Stats()
+    check(lib().bh_last_stats(C.byref(s), _stream(stream)))
+    pair = lambda a: {"fp64": int(a[0]), "fp32": int(a[1])}
+    return {"rays": s.rays, "cls": dict(zip(("sky", "captured", "disk", "unresolved", "invalid"),
+                                            (int(x) for x in s.cls))),
+            "path": dict(zip(("none", "fp64", "fp32", "surrogate"), (int(x) for x in s.path))),
+            "step_evals": s.step_evals, "accepted": pair(s.accepted), "rejected": pair(s.rejected),
+            "newton": pair(s.newton), "capped": pair(s.capped), "sur_listed": s.sur_listed,
+            "sur_fallback": s.sur_fallback, "sur_untrusted": s.sur_untrusted}
 
 
 KERNEL_CLASSES = ("setup", "integrate", "shade", "surrogate")

@@ -43,8 +43,9 @@ struct Workspace {
     int64_t cap = 0;
     void* base = nullptr;
     bh::Work w{};
-    unsigned long long* counts = nullptr;  // 4 counters for bh_last_counts
+    unsigned long long* counts = nullptr;  // 32 counters: bh_last_counts, bh_last_stats
     int64_t last_n = 0;
+    bool last_stats = false;               // the last call collected statistics
     int cus = 0;
 };
 
@@ -206,6 +207,8 @@ bh_status check_opt(const bh_options* o) {
     if (o->chunk % 64 != 0) return fail(BH_ERR_ARG, "chunk must be a multiple of 64");
     if (o->refill_fp32 < 0 || o->refill_fp32 > 64 || o->refill_fp64 < 0 || o->refill_fp64 > 64)
         return fail(BH_ERR_ARG, "refill thresholds must be in [0, 64]");
+    if (o->collect_stats != 0 && o->collect_stats != 1)
+        return fail(BH_ERR_ARG, "collect_stats must be 0 or 1");
     return BH_OK;
 }
 
@@ -265,6 +268,7 @@ bh::DevRoute dev_route(const bh_options* o, const bh_scene* sc) {
     r.band = o->band_halfwidth * sc->M;
     r.trust = nullptr;
     r.r0m = 0.0f;
+    r.stats = nullptr;
     return r;
 }
 
@@ -373,6 +377,8 @@ bh_status run_on(const bh::Work& ws_w, int cus, const bh::Source& src, bool expl
     }
     bh::Work w = ws_w;
     if (!explicit_u0) w.u0 = nullptr;
+    const bool stats = opt->collect_stats != 0;
+    if (stats) rt.stats = reinterpret_cast<unsigned long long*>(w.ctr + bh::kCtrStats);
     hipError_t e = bh::launch_reset(w.ctr, stream);
     if (e != hipSuccess) return hip_fail(e, "reset");
     int t = timed ? timing_begin(0, stream) : -1;
@@ -390,7 +396,7 @@ bh_status run_on(const bh::Work& ws_w, int cus, const bh::Source& src, bool expl
             ? bh::launch_integrate_paper(src.n, explicit_u0, u0_uniform, sc, tol, opt->fixed_eps, w,
                                          cus, stream)
             : bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w,
-                                   cus, opt->grid_blocks, auto_chunk(opt), stream);
+                                   cus, opt->grid_blocks, auto_chunk(opt), stats, stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "integrate");
     t = timed ? timing_begin(2, stream) : -1;
@@ -412,7 +418,10 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     if (st != BH_OK) return st;
     st = run_on(ws->w, ws->cus, src, explicit_u0, u0_uniform, scene, opt, rgba, out, stream,
                 samples_side, true);
-    if (st == BH_OK) ws->last_n = src.n;
+    if (st == BH_OK) {
+        ws->last_n = src.n;
+        ws->last_stats = opt->collect_stats != 0;
+    }
     return st;
 }
 
@@ -546,6 +555,8 @@ bh_status bh_render_noalloc(const bh_camera* cam, const bh_scene* scene, const b
     int n = 1;
     bh_status st = render_source(cam, scene, opt, rgba, &src, &n);
     if (st != BH_OK) return st;
+    if (opt->collect_stats)
+        return fail(BH_ERR_UNSUPPORTED, "bh_render_noalloc does not collect statistics");
     if (src.n > BH_NOALLOC_MAX_RAYS)
         return fail(BH_ERR_ARG,
                     "bh_render_noalloc: %lld rays (width * height * samples_side^2) exceed its "
@@ -588,6 +599,47 @@ bh_status bh_last_counts(int64_t counts[4], void* stream) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     for (int k = 0; k < 4; ++k) counts[k] = (int64_t)h[k];
+    return BH_OK;
+}
+
+bh_status bh_last_stats(bh_stats* st, void* stream) {
+    if (!st) return fail(BH_ERR_ARG, "st is NULL");
+    Workspace* ws = nullptr;
+    bh_status rc = get_workspace(0, (hipStream_t)stream, &ws);
+    if (rc != BH_OK) return rc;
+    if (!ws->last_stats || ws->last_n == 0)
+        return fail(BH_ERR_STATE, "the last call on this device did not collect statistics");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemsetAsync(ws->counts, 0, 10 * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    e = bh::launch_stats(ws->last_n, ws->w, ws->counts, s);
+    if (e != hipSuccess) return hip_fail(e, "stats");
+    unsigned long long h[10];
+    std::vector<int32_t> ctr(bh::kCtrInts);
+    e = hipMemcpyAsync(h, ws->counts, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctr.data(), ws->w.ctr, sizeof(int32_t) * bh::kCtrInts,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading the statistics");
+    unsigned long long c[bh::kStatSlots];
+    memcpy(c, ctr.data() + bh::kCtrStats, sizeof c);
+    *st = bh_stats{};
+    st->rays = ws->last_n;
+    for (int k = 0; k < 5; ++k) st->cls[k] = (int64_t)h[k];
+    for (int k = 0; k < 4; ++k) st->path[k] = (int64_t)h[5 + k];
+    st->step_evals = (int64_t)h[9];
+    for (int k = 0; k < 2; ++k) {
+        st->accepted[k] = (int64_t)c[4 * k];
+        st->rejected[k] = (int64_t)c[4 * k + 1];
+        st->newton[k] = (int64_t)c[4 * k + 2];
+        st->capped[k] = (int64_t)c[4 * k + 3];
+    }
+    int64_t listed = 0;
+    for (int q = 0; q < bh::kSurSlices; ++q) listed += ctr[bh::kCtrSur + q * bh::kCtrStride];
+    st->sur_listed = listed;
+    st->sur_fallback = listed - st->path[BH_PATH_SURROGATE];
+    st->sur_untrusted = (int64_t)c[8];
     return BH_OK;
 }
 
@@ -662,6 +714,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     bh_status st = check_opt(opt);
     if (st != BH_OK) return st;
     if (opt->surrogate) return fail(BH_ERR_UNSUPPORTED, "batches do not route to the surrogate");
+    if (opt->collect_stats) return fail(BH_ERR_UNSUPPORTED, "batches do not collect statistics");
     if (opt->samples_side > 1) return fail(BH_ERR_UNSUPPORTED, "batches trace one ray per pixel");
     if (opt->fixed_eps > 0.0) return fail(BH_ERR_UNSUPPORTED, "batches use adaptive steps");
     std::vector<bh::ReqDev> req(n);

@@ -97,6 +97,7 @@ struct DevRoute {
     double band;              // half-width of the critical band, absolute units
     const uint8_t* trust;     // surrogate trust map, or NULL: no surrogate routing
     float r0m;                // camera distance / M (surrogate routing only)
+    unsigned long long* stats;// per-call statistics (kCtrStats), or NULL: not collected
 };
 
 // Per-ray workspace (structure of arrays, capacity >= rays of the call).
@@ -129,7 +130,13 @@ constexpr int kCtrBand = kCtrStride;                    // band queue head
 constexpr int kCtrMain = 2 * kCtrStride;                // kSlices main-queue heads
 constexpr int kSurSlices = 64;                          // surrogate-list slices
 constexpr int kCtrSur = kCtrMain + kSlices * kCtrStride; // kSurSlices surrogate-list lengths
-constexpr int kCtrInts = kCtrSur + kSurSlices * kCtrStride;
+// Per-call statistics (bh_last_stats), 64-bit counters: for the FP64 rays
+// [0..3] and the FP32 rays [4..7] accepted steps, rejected trial steps,
+// Newton re-steps and rays ended by a cap; [8] rays eligible for the
+// surrogate whose trust bin was not trusted.
+constexpr int kCtrStats = kCtrSur + kSurSlices * kCtrStride;
+constexpr int kStatSlots = 16;
+constexpr int kCtrInts = kCtrStats + 2 * kStatSlots;
 
 // The surrogate list is filled at set-up in kSurSlices slices, one per
 // residue of the set-up block index mod kSurSlices (one atomic per block on
@@ -229,7 +236,8 @@ hipError_t launch_setup(const Source& src, const DevScene& sc, const DevRoute& r
                         double* out_b, hipStream_t s);
 hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, const DevScene& sc,
                             const DevTol& tol, int precision, const Work& w, int cus,
-                            int grid_blocks, int chunk, hipStream_t s);
+                            int grid_blocks, int chunk, bool stats, hipStream_t s);
+hipError_t launch_stats(int64_t n, const Work& w, unsigned long long* out, hipStream_t s);
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
                         const Out& out, int precision, hipStream_t s);
 hipError_t launch_shade_samples(const Source& src, const DevScene& sc, const Work& w, float* rgba,

@@ -219,6 +219,7 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
             (!sc.has_disk || sc.urout * sc.urout * (1.0 - 2.0 * sc.M * sc.urout) > E0)) {
             const int bin = trust_bin((float)(b / sc.M), rt.r0m);
             sur = bin >= 0 && rt.trust[bin] != 0;
+            if (rt.stats && !sur) atomicAdd(&rt.stats[8], 1ull);
         }
         if (rt.analytic_capture && !sc.has_disk && B.p < 0.0 && b < bc - rt.band) {
             cls = CAPTURED;  // below the potential peak: falls in, no disk to hit
@@ -639,7 +640,10 @@ template <typename A, typename B> struct Pick<false, A, B> { using type = B; };
 // request index selects its entry.
 // R32 (FP32 batches): main-queue start records come from a.w.rec32 and result
 // records go to a.w.res32.
-template <typename T, bool VIRTUAL, bool BATCH, bool R32, bool KAPPA>
+// STATS: count accepted, rejected and Newton steps and capped rays into
+// the per-call statistics (an instrumented variant; the default one counts
+// nothing).
+template <typename T, bool VIRTUAL, bool BATCH, bool R32, bool KAPPA, bool STATS = false>
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
                           int nslices, T rtol, T ntol, const BatchConst* __restrict__ bct,
@@ -672,6 +676,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     int cnext = 0, cend = 0;
     bool drained = false;
     int slice = (int)(blockIdx.x % (unsigned)nslices), dry = 0;
+    // per-lane statistics over all its rays (STATS only)
+    int n_acc = 0, n_rej = 0, n_newt = 0, n_cap = 0;
 
     for (;;) {
         // ---- (A) idle lanes start their prefetched rays, once at least
@@ -740,7 +746,22 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // dry.  (A wavefront with no active lane otherwise runs one step with
         // every lane masked off, at its start and while the queue drains;
         // the loop keeps a single back edge.)
-        if (drained && cnext >= cend && __ballot(active || pf_valid) == 0) break;
+        if (drained && cnext >= cend && __ballot(active || pf_valid) == 0) {
+            if constexpr (STATS) {
+                // one atomic per counter and wavefront
+                unsigned long long* st =
+                    reinterpret_cast<unsigned long long*>(a.w.ctr + kCtrStats) + (sizeof(T) == 4 ? 4 : 0);
+                const int c4[4] = {n_acc, n_rej, n_newt, n_cap};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int x = c4[q];
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+                    if (lane == 0 && x) atomicAdd(&st[q], (unsigned long long)x);
+                }
+            }
+            break;
+        }
 
         // ---- (B) one step evaluation per lane ------------------------------
         const bool nrm = active & !refine;            // normal trial step
@@ -788,6 +809,11 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // The accepted crossing step gives the first update; each refinement
         // step gives one more (at most four updates).
         const bool newton = (active & refine) | skyx;
+        if constexpr (STATS) {
+            n_acc += acc ? 1 : 0;
+            n_rej += (go & !fits) ? 1 : 0;
+            n_newt += (active & refine) ? 1 : 0;
+        }
         const T dh = (vn - vsky) * recip(wn);
         const T hh_new = ht - dh;
         // (it is 0 until a ray's first sky crossing: set at the ray's start,
@@ -817,6 +843,7 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
 
         // A finished ray stores its result record.
         if (capped | disk_hit | capture | sky_done | over) {
+            if constexpr (STATS) n_cap += (capped | over) ? 1 : 0;
             const uint8_t cls = (capped | over) ? UNRESOLVED
                                 : disk_hit       ? DISK
                                 : capture        ? CAPTURED
@@ -861,10 +888,10 @@ __device__ __forceinline__ const BatchConst* stage_consts(const IntegArgs& a) {
 
 // FP64 mode: one pass over all rays tagged FP64.  KAPPA: some ray's scene
 // is flat (M = 0), so g keeps its factor k.
-template <bool BATCH, bool KAPPA>
+template <bool BATCH, bool KAPPA, bool STATS = false>
 __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
     const BatchConst* bct = stage_consts<BATCH>(a);
-    run_queue<double, true, BATCH, false, KAPPA>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
+    run_queue<double, true, BATCH, false, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
                                                  kSlices, a.tol.rtol64, a.tol.newton64, bct,
                                                  a.tol.refill64);
 }
@@ -875,34 +902,34 @@ __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
 // latency-bound; their waves start with the launch and run at raised issue
 // priority, so the FP32 waves sharing their SIMDs fill the gaps and the band
 // ends inside the FP32 work instead of trailing it.
-template <bool BATCH, bool KAPPA>
+template <bool BATCH, bool KAPPA, bool STATS = false>
 __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_blocks) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     if ((int)blockIdx.x < band_blocks) {
         __builtin_amdgcn_s_setprio(3);
         IntegArgs ab = a;
         ab.chunk = 64;
-        run_queue<double, false, BATCH, BATCH, KAPPA>(ab, a.w.q64, a.w.q64rec,
+        run_queue<double, false, BATCH, BATCH, KAPPA, STATS>(ab, a.w.q64, a.w.q64rec,
                                                       a.w.ctr[kCtrBandSize], &a.w.ctr[kCtrBand], 1,
                                                       a.tol.rtol64, a.tol.newton64, bct, 1);
         __builtin_amdgcn_s_setprio(0);
     }
-    run_queue<float, true, BATCH, BATCH, KAPPA>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
+    run_queue<float, true, BATCH, BATCH, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
                                                 kSlices, a.tol.rtol32, a.tol.newton32, bct,
                                                 a.tol.refill32);
 }
 
-template <bool KAPPA>
+template <bool KAPPA, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
-    integrate_fp64<false, KAPPA>(a);
+    integrate_fp64<false, KAPPA, STATS>(a);
 }
 
 // Held to 64 VGPRs (8 waves per SIMD for the FP32 rays); the FP64 band code
 // spills a few registers, which only band waves pay.
-template <bool KAPPA>
+template <bool KAPPA, bool STATS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
 k_integrate_fp32(IntegArgs a, int band_blocks) {
-    integrate_fp32<false, KAPPA>(a, band_blocks);
+    integrate_fp32<false, KAPPA, STATS>(a, band_blocks);
 }
 
 // Batch kernels: per-request constants come from LDS.
@@ -1298,6 +1325,29 @@ __global__ __launch_bounds__(kBlock) void k_shade_samples(Source src, DevScene s
                                                      acc.w * inv);
 }
 
+// Per-call statistics of the last single render or trace: out[0..4] rays per
+// class, out[5..8] rays per path, out[9] summed step evaluations.
+__global__ __launch_bounds__(kBlock) void k_stats(int64_t n, const int32_t* __restrict__ clst,
+                                                  const uint8_t* __restrict__ path,
+                                                  unsigned long long* out) {
+    __shared__ unsigned long long c[10];
+    if (threadIdx.x < 10) c[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long steps = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int32_t cs = clst[i];
+        const uint8_t p = path[i];
+        const int cl = cs & 7;
+        atomicAdd(&c[cl < 5 ? cl : 4], 1ull);
+        if (p < 4) atomicAdd(&c[5 + p], 1ull);
+        steps += (unsigned long long)(uint32_t)cs >> 3;
+    }
+    atomicAdd(&c[9], steps);
+    __syncthreads();
+    if (threadIdx.x < 10) atomicAdd(&out[threadIdx.x], c[threadIdx.x]);
+}
+
 // Batch start time and completion counters.
 __global__ void k_batch_begin(BatchDev b) {
     for (int r = threadIdx.x; r < b.nreq; r += blockDim.x) b.done[r] = 0;
@@ -1366,25 +1416,25 @@ static unsigned persistent_grid(int64_t n, int cus, int per_cu, int grid_blocks)
     return (unsigned)(g > 0 ? g : 1);
 }
 
-template <bool KAPPA>
+template <bool KAPPA, bool STATS>
 static void launch_integrate_k(const IntegArgs& a, int precision, int cus, int grid_blocks,
                                hipStream_t s) {
     static int occ64 = 0, occ32 = 0;  // per variant
     if (precision != 1) {
-        const unsigned g = persistent_grid(a.n, cus, blocks_per_cu(k_integrate_fp64<KAPPA>, &occ64),
-                                           grid_blocks);
-        k_integrate_fp64<KAPPA><<<g, kBlock, 0, s>>>(a);
+        const unsigned g = persistent_grid(
+            a.n, cus, blocks_per_cu(k_integrate_fp64<KAPPA, STATS>, &occ64), grid_blocks);
+        k_integrate_fp64<KAPPA, STATS><<<g, kBlock, 0, s>>>(a);
     } else {
-        const unsigned g = persistent_grid(a.n, cus, blocks_per_cu(k_integrate_fp32<KAPPA>, &occ32),
-                                           grid_blocks);
+        const unsigned g = persistent_grid(
+            a.n, cus, blocks_per_cu(k_integrate_fp32<KAPPA, STATS>, &occ32), grid_blocks);
         const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
-        k_integrate_fp32<KAPPA><<<g, kBlock, 0, s>>>(a, band_blocks);
+        k_integrate_fp32<KAPPA, STATS><<<g, kBlock, 0, s>>>(a, band_blocks);
     }
 }
 
 hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, const DevScene& sc,
                             const DevTol& tol, int precision, const Work& w, int cus,
-                            int grid_blocks, int chunk, hipStream_t s) {
+                            int grid_blocks, int chunk, bool stats, hipStream_t s) {
     if (n == 0) return hipSuccess;
     IntegArgs a;
     a.n = n;
@@ -1397,8 +1447,13 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
     a.bconst = nullptr;
     a.nreq = 0;
     a.fc = integ_consts(sc, tol, u0_uniform);
-    if (sc.M > 0.0) launch_integrate_k<false>(a, precision, cus, grid_blocks, s);
-    else launch_integrate_k<true>(a, precision, cus, grid_blocks, s);
+    if (stats) {
+        if (sc.M > 0.0) launch_integrate_k<false, true>(a, precision, cus, grid_blocks, s);
+        else launch_integrate_k<true, true>(a, precision, cus, grid_blocks, s);
+    } else {
+        if (sc.M > 0.0) launch_integrate_k<false, false>(a, precision, cus, grid_blocks, s);
+        else launch_integrate_k<true, false>(a, precision, cus, grid_blocks, s);
+    }
     return hipGetLastError();
 }
 
@@ -1506,6 +1561,14 @@ hipError_t launch_integrate_paper(int64_t n, bool explicit_u0, double u0_uniform
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g > (int64_t)cus * 16) g = (int64_t)cus * 16;
     k_integrate_paper<<<(unsigned)g, kBlock, 0, s>>>(a, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(int64_t n, const Work& w, unsigned long long* out, hipStream_t s) {
+    unsigned g = blocks_for(n);
+    if (g > 4096) g = 4096;
+    if (g == 0) g = 1;
+    k_stats<<<g, kBlock, 0, s>>>(n, w.clst, w.path, out);
     return hipGetLastError();
 }
 

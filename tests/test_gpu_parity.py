@@ -251,6 +251,51 @@ def test_step_counts_track_oracle(bh, ref):
     assert abs(g / o - 1.0) < 0.08, (g, o)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_stats_account_for_every_ray_and_step(bh, ref, precision):
+    """bh_last_stats (collect_stats = 1): the instrumented integrator gives the
+    same image and records as the plain one; the per-class and per-path ray
+    counts match the per-ray records; accepted + rejected + Newton steps add
+    up to the per-ray step evaluations; capped rays are the UNRESOLVED ones;
+    and in FP64 mode the accepted and rejected steps track the oracle's (same
+    controller, same tolerance) within 2%."""
+    f = inputs.disk_1024(160)
+    p = bh.FP64 if precision == "fp64" else bh.FP32
+    rgba0, out0 = gpu_render(bh, f, p)
+    with pytest.raises(bh.BhError) as e:
+        bh.last_stats()
+    assert e.value.status == bh.BH_ERR_STATE
+    rgba, out = gpu_render(bh, f, p, collect_stats=1)
+    np.testing.assert_array_equal(rgba, rgba0)
+    for k in ("cls", "phi_end", "r_hit", "steps", "path"):
+        np.testing.assert_array_equal(out[k], out0[k])
+    st = bh.last_stats()
+    n = f.camera.width * f.camera.height
+    assert st["rays"] == n
+    for c, name in enumerate(("sky", "captured", "disk", "unresolved", "invalid")):
+        assert st["cls"][name] == int((out["cls"] == c).sum()), name
+    for q, name in enumerate(("none", "fp64", "fp32", "surrogate")):
+        assert st["path"][name] == int((out["path"] == q).sum()), name
+    assert st["step_evals"] == int(out["steps"].astype(np.int64).sum())
+    tot = sum(st[k]["fp64"] + st[k]["fp32"] for k in ("accepted", "rejected", "newton"))
+    assert tot == st["step_evals"]
+    assert st["capped"]["fp64"] + st["capped"]["fp32"] == st["cls"]["unresolved"]
+    # every integrated ray takes at least one accepted step
+    integrated = int((out["path"] == bh.PATH_FP64).sum() + (out["path"] == bh.PATH_FP32).sum())
+    assert st["accepted"]["fp64"] + st["accepted"]["fp32"] >= integrated
+    if precision == "fp32":
+        assert st["accepted"]["fp32"] > 0 and st["accepted"]["fp64"] > 0  # the band
+    else:
+        assert st["accepted"]["fp32"] == 0 and st["newton"]["fp32"] == 0
+        _, r = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))
+        integ = (out["path"] == bh.PATH_FP64)
+        oa, orj = int(r.n_acc[integ].sum()), int(r.n_rej[integ].sum())
+        assert abs(st["accepted"]["fp64"] / oa - 1.0) < 0.02, (st["accepted"], oa)
+        assert abs(st["rejected"]["fp64"] - orj) <= 0.02 * oa, (st["rejected"], orj)
+    print(f"{precision}: accepted {st['accepted']}, rejected {st['rejected']}, "
+          f"newton {st['newton']} over {integrated} integrated rays")
+
+
 def test_counts(bh):
     import torch
     f = inputs.plain_64()

@@ -249,14 +249,23 @@ def test_new_parameters_invalidate_the_trust_map(bh, trained):
     import torch
     sur, _ = trained
     f = max(inputs.orbit_4k(), key=lambda fr: fr.camera.r / fr.scene.M)
-    opt = bh.options(precision=bh.FP32)
+    opt = bh.options(precision=bh.FP32, collect_stats=1)
     opt.surrogate = sur.handle
     bh.render(f.camera, f.scene, opt)
-    assert bh.last_counts()["surrogate"] > 0
+    served = bh.last_counts()["surrogate"]
+    assert served > 0
+    # the statistics account for the surrogate's rays: listed at set-up =
+    # served + handed back; eligible rays in untrusted bins are counted
+    st = bh.last_stats()
+    assert st["path"]["surrogate"] == served
+    assert st["sur_listed"] == served + st["sur_fallback"] and st["sur_fallback"] >= 0
+    assert st["sur_untrusted"] >= 0
     params, m, v, trust = sur.get(0), sur.get(2), sur.get(3), sur.trust()
     sur.set(params, m, v)
     bh.render(f.camera, f.scene, opt)
     assert bh.last_counts()["surrogate"] == 0
+    st = bh.last_stats()
+    assert st["sur_listed"] == 0 and st["sur_untrusted"] == 0  # no map: no routing at all
     sur.set_trust(trust)
     bh.render(f.camera, f.scene, opt)
     assert bh.last_counts()["surrogate"] > 0
