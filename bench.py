@@ -335,7 +335,7 @@ def main() -> int:
         line["paper_mode_sweep"] = paper_leg(sweep, api)
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg(args, frames, bufs, api, torch, value_frames, step_frames,
-                                         sweep)
+                                         sweep, value)
         if sweep is not None:
             line["paper_mode_sweep"]["adaptive_fp32_band_surrogate"] = line["surrogate"].pop("sweep_point")
     
@@ -539,7 +539,7 @@ FLOP_PER_SUR_RAY = 66560     # 2 x (2*128 + 128*128 + 128*128 + 128*2) multiply-
 PEAK_BF16_TFLOPS = 2500.0    # dense BF16 matrix-core peak
 
 
-def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None):
+def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None, value_batch=None):
     """Trains the network on the GPU (4M escape-side + 1M capture-side FP64
     labels, Adam), builds its trust map, then renders the same frames with
     FP32 + band + surrogate.  Reports the throughput, the gain over the
@@ -589,6 +589,27 @@ def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None):
     ach = (sur_rays_launch * FLOP_PER_SUR_RAY / (sur_ms / sur_n * 1e-3) / 1e12) if sur_n else 0.0
     value = rays / (ms * 1e-3) / 1e6
     point = sweep.point(lambda f: opt) if sweep is not None else None
+    # the same frames as one batch with the network (one inference launch
+    # over every frame's listed rays), against the FP32 + band batch
+    opt_b = api.options(precision=api.FP32, rtol_fp32=args.rtol_fp32, batch_groups=1)
+    opt_b.surrogate = sur.handle
+    bt = api.Batch(frames, opt_b, use_graph=False, images=bufs)
+    for _ in range(args.warmup):
+        bt.launch()
+    torch.cuda.synchronize()
+    api.timing_enable(True)
+    api.timing_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.launch()
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1e3 / args.steps
+    tim_b = api.timing_read()
+    api.timing_enable(False)
+    bt.close()
+    value_b = rays / (ms_b * 1e-3) / 1e6
+    bsur_ms, bsur_n = tim_b.get("surrogate", (0.0, 0))
+    ach_b = (n_sur * FLOP_PER_SUR_RAY / (bsur_ms / bsur_n * 1e-3) / 1e12) if bsur_n else 0.0
     sur.close()
     res = {
         "value": round(value, 2), "unit": "Mrays/s", "ms_per_step": round(ms, 4),
@@ -596,6 +617,12 @@ def surrogate_leg(args, frames, bufs, api, torch, value_fast, step, sweep=None):
         "share": round(n_sur / rays, 4),
         "max_exit_err_rad_vs_fp64": max_err,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
+        "batch": {"value": round(value_b, 2), "unit": "Mrays/s", "ms_per_step": round(ms_b, 4),
+                  "gain_vs_fp32_band_batch": (round(value_b / value_batch, 4)
+                                              if value_batch else None),
+                  "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim_b.items()},
+                  "sur_render_tflops": round(ach_b, 2),
+                  "sur_render_frac_of_bf16_peak": round(ach_b / PEAK_BF16_TFLOPS, 4)},
         "fit": {"seconds": round(fit_s, 1), "train_samples": rep["train_samples"],
                 "epochs": rep["epochs"], "final_loss": rep["final_loss"],
                 "trusted_bins": rep["trusted_bins"],

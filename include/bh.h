@@ -241,8 +241,12 @@ bh_status bh_last_stats(bh_stats* st, void* stream);
  * device clock.  Groups run one after another, so early requests complete
  * early.  With use_graph the whole sequence is captured once into a hipGraph
  * and each bh_batch_launch replays it.  Output pixels are bit-identical to
- * bh_render of each request with the same options.  The surrogate is not
- * used in batches.
+ * bh_render of each request with the same options.  With opt->surrogate set
+ * (FP32), each group's set-up also lists the rays of eligible requests (as
+ * bh_render would: M > 0, sky at 1000 M, a valid trust map) for one
+ * inference launch before its integrator; the network must outlive the
+ * batch, and a launch after its parameters or trust map changed returns
+ * BH_ERR_STATE.
  * ------------------------------------------------------------------------- */
 typedef struct {
     bh_camera cam;
@@ -260,9 +264,10 @@ typedef struct {
 typedef struct bh_batch bh_batch;
 
 /* Validates the requests (as bh_render), allocates the batch's device tables
- * and per-ray workspace (~60 bytes per ray), and with use_graph != 0 captures
- * the launch sequence into a hipGraph.  The request array is copied; the
- * output pointers are kept.  Synchronous. */
+ * and per-ray workspace (~60 bytes per ray, ~20 more with the surrogate), and
+ * with use_graph != 0 captures the launch sequence into a hipGraph.  The
+ * request array is copied; the output pointers are kept.  samples_side > 1,
+ * fixed_eps > 0 and collect_stats are BH_ERR_UNSUPPORTED.  Synchronous. */
 bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, int use_graph,
                           bh_batch** out);
 /* Enqueues one execution of the batch on `stream`. */

@@ -664,6 +664,14 @@ struct bh_batch {
     // first ray) and the group's slice of the per-ray workspace
     std::vector<bh::BatchDev> gdev;
     std::vector<bh::Work> gw;
+    std::vector<int> gfirst;  // first request of each group (the tables' rq are group-local)
+    // surrogate routing (FP32 batches with a trusted network): the network,
+    // its parameter/trust version at creation, its inference pack and the
+    // per-request constants of its inference
+    const bh_surrogate* sur = nullptr;
+    unsigned sur_version = 0;
+    const void* sur_pack = nullptr;
+    const bh::SurReq* sur_req = nullptr;
 };
 
 namespace {
@@ -676,6 +684,13 @@ hipError_t launch_groups(const bh_batch* b, hipStream_t s, bool timed) {
         e = bh::launch_batch_setup(b->gdev[g], b->gw[g], s);
         timing_end(t, s);
         if (e != hipSuccess) break;
+        if (b->sur_pack && b->gdev[g].any_sur) {
+            t = timed ? timing_begin(3, s) : -1;
+            e = bh::launch_surrogate_render_batch(b->gdev[g].total, b->gw[g], b->sur_pack,
+                                                  b->sur_req + b->gfirst[g], b->cus, s);
+            timing_end(t, s);
+            if (e != hipSuccess) break;
+        }
         t = timed ? timing_begin(1, s) : -1;
         e = bh::launch_batch_integrate(b->gdev[g], b->gw[g], b->tol, b->precision, b->cus,
                                        b->grid_blocks, b->chunk, s);
@@ -713,14 +728,19 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     if (!reqs || n < 1) return fail(BH_ERR_ARG, "need at least one request");
     bh_status st = check_opt(opt);
     if (st != BH_OK) return st;
-    if (opt->surrogate) return fail(BH_ERR_UNSUPPORTED, "batches do not route to the surrogate");
     if (opt->collect_stats) return fail(BH_ERR_UNSUPPORTED, "batches do not collect statistics");
     if (opt->samples_side > 1) return fail(BH_ERR_UNSUPPORTED, "batches trace one ray per pixel");
     if (opt->fixed_eps > 0.0) return fail(BH_ERR_UNSUPPORTED, "batches use adaptive steps");
     std::vector<bh::ReqDev> req(n);
     std::vector<bh::BatchConst> bc(n);
+    std::vector<bh::SurReq> sreq(n);
+    std::vector<int> routes(n, 0);
     std::vector<int64_t> off(n + 1, 0);
-    int any_flat = 0;
+    int any_flat = 0, any_sur = 0;
+    // The surrogate serves FP32 requests whose sky is at 1000 M (the radius it
+    // was trained for), while its trust map is valid.
+    const uint8_t* trust = opt->surrogate && opt->precision == BH_FP32
+                               ? bh::surrogate_trust(opt->surrogate) : nullptr;
     for (int r = 0; r < n; ++r) {
         const bh_request& q = reqs[r];
         if ((st = check_scene(&q.scene)) != BH_OK) return fail(st, "request %d: %s", r, bh_last_error());
@@ -734,6 +754,15 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         const bh::DevTol t = dev_tol(opt, &q.scene);
         bc[r] = bh::integ_consts(req[r].sc, t, 1.0 / q.cam.r);
         any_flat = any_flat || !(q.scene.M > 0.0);
+        sreq[r] = bh::SurReq{0.0, 0.0f, 0.0f};
+        if (trust && q.scene.M > 0.0 && fabs(q.scene.r_sky / q.scene.M - 1000.0) < 1e-9) {
+            req[r].rt.trust = trust;
+            req[r].rt.r0m = (float)(q.cam.r / q.scene.M);
+            sreq[r] = bh::SurReq{1.0 / q.scene.M, (float)(q.cam.r / q.scene.M),
+                                 (float)(q.scene.M / q.cam.r)};
+            routes[r] = 1;
+            any_sur = 1;
+        }
         off[r + 1] = off[r] + (int64_t)q.cam.width * q.cam.height;
     }
     if (off[n] > INT32_MAX) return fail(BH_ERR_ARG, "a batch must have < 2^31 rays");
@@ -767,8 +796,14 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         for (int r = gr[g]; r <= gr[g + 1]; ++r) goff.push_back(off[r] - off[gr[g]]);
     const size_t tables = align256(sizeof(int64_t) * (n + 1)) + align256(sizeof(bh::ReqDev) * n) +
                           align256(sizeof(bh::BatchConst) * n) + align256(8 * (size_t)n) +
-                          align256(8 * (size_t)(n + 1)) + align256(sizeof(int64_t) * goff.size());
-    const size_t total = 3 * sz16 + 3 * sz4 + sz1 + szc + tables;
+                          align256(8 * (size_t)(n + 1)) + align256(sizeof(int64_t) * goff.size()) +
+                          align256(sizeof(bh::SurReq) * n);
+    // the surrogate list (rays of one group at a time), sized for the largest group
+    int64_t gmax = 0;
+    for (int g = 0; g < G; ++g) gmax = std::max(gmax, off[gr[g + 1]] - off[gr[g]]);
+    const int64_t scap = any_sur ? bh::kSurSlices * bh::sur_slice_cap(gmax) : 0;
+    const size_t szs = align256((size_t)scap * 16) + align256((size_t)scap * 4);
+    const size_t total = 3 * sz16 + 3 * sz4 + sz1 + szc + tables + szs;
     e = hipMalloc(&b->base, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -789,16 +824,22 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     b->w.u0 = nullptr;
     b->w.qsur = nullptr;
     b->w.qsurrec = nullptr;
+    if (any_sur) {
+        b->w.qsurrec = (double2*)c; c += align256((size_t)scap * 16);
+        b->w.qsur = (int32_t*)c; c += align256((size_t)scap * 4);
+    }
     int64_t* d_off = (int64_t*)c; c += align256(sizeof(int64_t) * (n + 1));
     bh::ReqDev* d_req = (bh::ReqDev*)c; c += align256(sizeof(bh::ReqDev) * n);
     bh::BatchConst* d_bc = (bh::BatchConst*)c; c += align256(sizeof(bh::BatchConst) * n);
     unsigned long long* d_done = (unsigned long long*)c; c += align256(8 * (size_t)n);
     unsigned long long* d_stamp = (unsigned long long*)c; c += align256(8 * (size_t)(n + 1));
+    bh::SurReq* d_sreq = (bh::SurReq*)c; c += align256(sizeof(bh::SurReq) * n);
     int64_t* d_goff = (int64_t*)c;
     if ((e = hipMemcpy(d_off, off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d_goff, goff.data(), sizeof(int64_t) * goff.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d_req, req.data(), sizeof(bh::ReqDev) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d_bc, bc.data(), sizeof(bh::BatchConst) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_sreq, sreq.data(), sizeof(bh::SurReq) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(d_stamp, 0, 8 * (size_t)(n + 1))) != hipSuccess)
         return cleanup(hip_fail(e, "batch tables"));
     bh::BatchDev& d = b->dev;
@@ -811,6 +852,13 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     d.stamp = d_stamp;
     d.req_host0 = req[0].sc;
     d.any_flat = any_flat;
+    d.any_sur = any_sur;
+    if (any_sur) {
+        b->sur = opt->surrogate;
+        b->sur_version = bh::surrogate_version(opt->surrogate);
+        b->sur_pack = bh::surrogate_pack(opt->surrogate);
+        b->sur_req = d_sreq;
+    }
     for (int g = 0, k = 0; g < G; ++g) {
         const int r0 = gr[g], ng = gr[g + 1] - gr[g];
         const int64_t base = off[r0];
@@ -822,6 +870,8 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         dg.bconst = d_bc + r0;
         dg.done = d_done + r0;
         dg.stamp = d_stamp + r0;
+        dg.any_sur = 0;
+        for (int r = r0; r < r0 + ng; ++r) dg.any_sur |= routes[r];
         k += ng + 1;
         bh::Work wg = b->w;
         wg.rec += base;
@@ -833,6 +883,7 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
         wg.path += base;
         b->gdev.push_back(dg);
         b->gw.push_back(wg);
+        b->gfirst.push_back(r0);
     }
     if (b->use_graph) {
         // Capture the whole sequence (counter resets are kernels, not memsets)
@@ -857,6 +908,9 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
 
 bh_status bh_batch_launch(bh_batch* b, void* stream) {
     if (!b) return fail(BH_ERR_ARG, "batch is NULL");
+    if (b->sur && bh::surrogate_version(b->sur) != b->sur_version)
+        return fail(BH_ERR_STATE, "the surrogate's parameters or trust map changed since the batch "
+                                  "was created; create the batch again");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (b->use_graph)

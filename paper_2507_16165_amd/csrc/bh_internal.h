@@ -208,6 +208,13 @@ struct ReqDev {
     float* rgba;
 };
 
+// Per-request constants of the surrogate's batch inference (surrogate-routed
+// requests: M > 0 and the sky at 1000 M).
+struct SurReq {
+    double inv_M;             // 1/M
+    float r0m, inv_r0m;       // camera distance / M and its reciprocal
+};
+
 struct BatchDev {
     int nreq;
     int64_t total;                 // rays of all requests
@@ -218,6 +225,7 @@ struct BatchDev {
     unsigned long long* stamp;     // finish clock per request; stamp[nreq] = start
     DevScene req_host0;            // unused placeholder scene for the integrator args
     int any_flat;                  // some request has M = 0 (integrator variant with k)
+    int any_sur;                   // some request routes rays to the surrogate
 };
 
 // Launch helpers (defined in bh_kernels.hip).
@@ -248,6 +256,13 @@ const uint8_t* surrogate_trust(const bh_surrogate* s);
 const void* surrogate_pack(const bh_surrogate* s);
 hipError_t launch_surrogate_render(int64_t n, const Work& w, const void* pack, double M,
                                    double r_cam, int cus, hipStream_t s);
+// The same over a batch group's list (FP32 batch records; w.rq gives each
+// ray's request within the group, whose constants are req[request]: the
+// group's slice of the table).
+hipError_t launch_surrogate_render_batch(int64_t n, const Work& w, const void* pack,
+                                         const SurReq* req, int cus, hipStream_t s);
+// A counter that changes whenever the network's parameters or trust map do.
+unsigned surrogate_version(const bh_surrogate* s);
 hipError_t launch_count_paths(int64_t n, const Work& w, unsigned long long* counts, hipStream_t s);
 
 }  // namespace bh

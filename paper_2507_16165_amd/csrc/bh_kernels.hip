@@ -415,11 +415,12 @@ __device__ __forceinline__ S uniform_load(const S* __restrict__ p) {
 }
 
 // Set-up of pixel i of request q (workspace index g) in a batch: FP32-mode
-// requests take the FP32 camera set-up, FP64-mode ones the FP64 set-up.
+// requests without surrogate routing take the FP32 camera set-up, the others
+// the FP64 set-up (which routes to the surrogate).
 template <bool R32>
 __device__ __forceinline__ int batch_ray(const ReqDev& q, int64_t i, int64_t g, const Work& w,
                                          double& b, double& w0, double& phi1) {
-    if (q.rt.precision == 1)
+    if (q.rt.precision == 1 && !q.rt.trust)
         return setup_camera32<true, R32>(q.cam, q.sc, q.rt, i, g, w, nullptr, b, w0, phi1);
     return setup_ray<true, R32>(camera_basis(q.cam, i, q.sc.M, q.sc.r_sky), q.sc, q.rt, g, w,
                                 nullptr, b, w0, phi1);
@@ -443,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
         const ReqDev q = uniform_load(b.req + r0);
         if (g < b.total) {
             w.rq[g] = r0;
-            to = batch_ray<R32>(q, g - s_off[r0], g, w, bi, w0, phi1);  // no surrogate routing
+            to = batch_ray<R32>(q, g - s_off[r0], g, w, bi, w0, phi1);
         }
     } else if (g < b.total) {
         const int r = find_req(s_off, b.nreq, g);
@@ -452,6 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_batch(BatchDev b, Work w) {
         to = batch_ray<R32>(q, g - s_off[r], g, w, bi, w0, phi1);
     }
     append_band(to == kToBand, g, w0, phi1, w);
+    if (b.any_sur) append_sur(to == kToSur, g, bi, w0, b.total, w);  // block-uniform
 }
 
 // ---------------------------------------------------------------------------

@@ -566,6 +566,9 @@ struct SurRender {
     float r0m;     // camera distance / M
     float inv_r0m; // M / camera distance
     double inv_M;  // 1/M
+    // batches: each listed ray's request (w.rq) selects these constants
+    // instead of the three above; NULL for a single render
+    const SurReq* req;
 };
 
 // The render path's exit azimuth in FP32 (its error budget is 1e-4 rad):
@@ -579,16 +582,23 @@ __device__ inline float sweep1f(float b, float ib, float ir0) {
     return 3.14159265f - a(b * (1.0f / 1000.0f)) - a(b * ir0);
 }
 
+// BATCH: FP32 batch records (rec32 / res32, no path byte), per-ray inv_r0m.
+template <bool BATCH>
 __device__ inline void sur_finish(const SurRender& a, int id, double w0, float bm, float y0,
-                                  float y1) {
+                                  float y1, float inv_r0m) {
     if (!(y1 < 0.0f)) {
-        a.w.rec[id] = make_double2(w0, a.w.rec[id].y);
-        a.w.path[id] = PATH_FP32;
+        if constexpr (BATCH) {
+            a.w.rec32[id] = make_float2((float)w0, a.w.rec32[id].y);
+        } else {
+            a.w.rec[id] = make_double2(w0, a.w.rec[id].y);
+            a.w.path[id] = PATH_FP32;
+        }
         return;
     }
     const float ib = __builtin_amdgcn_rcpf(bm);
-    const float phi = sweep1f(bm, ib, a.inv_r0m) + (12.0f * ib * ib) * y0;
-    a.w.res[id] = make_double2((double)phi, 0.0);
+    const float phi = sweep1f(bm, ib, inv_r0m) + (12.0f * ib * ib) * y0;
+    if constexpr (BATCH) a.w.res32[id] = make_float2(phi, 0.0f);
+    else a.w.res[id] = make_double2((double)phi, 0.0);
     a.w.clst[id] = 0;  // SKY, no integration steps
 }
 
@@ -617,6 +627,7 @@ __device__ inline SurEntry sur_entry(const int* cnt, const int* first, int64_t s
 // each weight operand read from LDS then feeds two matrix-core instructions.
 // With one tile per pass the four SIMDs of a CU need about 128 B of LDS reads
 // per clock at the matrix-core rate, the whole LDS bandwidth.
+template <bool BATCH>
 __global__ __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void k_sur_render(const void* __restrict__ pack, SurRender a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -669,21 +680,40 @@ void k_sur_render(const void* __restrict__ pack, SurRender a) {
         int idn[2];
         double2 recn[2];
         fetch(p + nw, en, idn, recn);
-        float bm[2], f1[2], f2[2] = {f2v, f2v}, y0[2], y1[2];
+        float bm[2], f1[2], f2[2] = {f2v, f2v}, y0[2], y1[2], ir0[2] = {a.inv_r0m, a.inv_r0m};
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            bm[k] = (float)(rec[k].x * a.inv_M);
+            if constexpr (BATCH) {
+                // the ray's request (an invalid lane reads entry 0: its
+                // values are computed and dropped)
+                const SurReq q = a.req[a.w.rq[id[k]]];
+                bm[k] = (float)(rec[k].x * q.inv_M);
+                f2[k] = feature2(q.r0m);
+                ir0[k] = q.inv_r0m;
+            } else {
+                bm[k] = (float)(rec[k].x * a.inv_M);
+            }
             f1[k] = feature1(bm[k]);
         }
         mlp_tiles<2>(pk, pkf, f1, f2, y0, y1);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            if (l < 32 && e[k].valid) sur_finish(a, id[k], rec[k].y, bm[k], y0[k], y1[k]);
+            if (l < 32 && e[k].valid)
+                sur_finish<BATCH>(a, id[k], rec[k].y, bm[k], y0[k], y1[k], ir0[k]);
             e[k] = en[k];
             id[k] = idn[k];
             rec[k] = recn[k];
         }
     }
+}
+
+// Two blocks per CU (the weights fill ~66 KB of LDS per block); blocks beyond
+// the list's tiles return at once.
+static unsigned sur_grid(int64_t n, int cus) {
+    int64_t g = (int64_t)cus * 2;
+    const int64_t need = (n + 64 * (kInferThreads / 64) - 1) / (64 * (kInferThreads / 64));
+    if (g > need) g = need > 0 ? need : 1;
+    return (unsigned)g;
 }
 
 hipError_t launch_surrogate_render(int64_t n, const Work& w, const void* pack, double M,
@@ -694,12 +724,23 @@ hipError_t launch_surrogate_render(int64_t n, const Work& w, const void* pack, d
     a.r0m = (float)(r_cam / M);
     a.inv_r0m = (float)(M / r_cam);
     a.inv_M = 1.0 / M;
-    // Two blocks per CU (the weights fill ~66 KB of LDS per block); blocks
-    // beyond the list's tiles return at once.
-    int64_t g = (int64_t)cus * 2;
-    const int64_t need = (n + 64 * (kInferThreads / 64) - 1) / (64 * (kInferThreads / 64));
-    if (g > need) g = need > 0 ? need : 1;
-    k_sur_render<<<(unsigned)g, kInferThreads, kPackBytes, s>>>(pack, a);
+    a.req = nullptr;
+    k_sur_render<false><<<sur_grid(n, cus), kInferThreads, kPackBytes, s>>>(pack, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_surrogate_render_batch(int64_t n, const Work& w, const void* pack,
+                                         const SurReq* req, int cus, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (!w.rec32 || !w.res32 || !w.rq || !req) return hipErrorInvalidValue;
+    SurRender a;
+    a.slice_cap = sur_slice_cap(n);
+    a.w = w;
+    a.r0m = 105.0f;  // unused: each ray's request gives its constants
+    a.inv_r0m = 0.0f;
+    a.inv_M = 0.0;
+    a.req = req;
+    k_sur_render<true><<<sur_grid(n, cus), kInferThreads, kPackBytes, s>>>(pack, a);
     return hipGetLastError();
 }
 
@@ -735,6 +776,7 @@ struct bh_surrogate {
     int64_t lab_cap = 0;
     int step = 0;
     int trusted = 0;
+    unsigned version = 0;  // changes with the parameters and the trust map
     int cus = 256;
 };
 
@@ -910,6 +952,7 @@ bh_status bh_surrogate_set_params(bh_surrogate* s, const float* params, const fl
     // the trust map was validated on the old parameters: renders stop routing
     // to the network until a map is built (or set) for these
     s->trusted = 0;
+    ++s->version;
     HIPCHK(repack(s, nullptr), "pack");
     HIPCHK(hipDeviceSynchronize(), "sync");
     return BH_OK;
@@ -979,6 +1022,7 @@ bh_status bh_surrogate_train_step(bh_surrogate* s, const double* b, const double
     if (hp && hp->lr > 0.0f) {
         s->step += 1;
         s->trusted = 0;  // new parameters: the trust map no longer applies
+        ++s->version;
         const float c1 = 1.0f / (1.0f - powf(hp->beta1, (float)s->step));
         const float c2 = 1.0f / (1.0f - powf(hp->beta2, (float)s->step));
         k_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(NPARAM, s->P, s->G, s->m, s->v, hp->lr,
@@ -1060,6 +1104,7 @@ bh_status bh_surrogate_build_trust(bh_surrogate* s, const double* b, const doubl
                                                                  s->trust);
     HIPCHK(hipGetLastError(), "trust");
     s->trusted = 1;
+    ++s->version;
     return BH_OK;
 }
 
@@ -1077,6 +1122,7 @@ bh_status bh_surrogate_set_trust(bh_surrogate* s, const uint8_t* host_map, int64
     HIPCHK(hipDeviceSynchronize(), "sync");
     HIPCHK(hipMemcpy(s->trust, host_map, count, hipMemcpyHostToDevice), "upload");
     s->trusted = 1;
+    ++s->version;
     return BH_OK;
 }
 
@@ -1084,5 +1130,6 @@ bh_status bh_surrogate_set_trust(bh_surrogate* s, const uint8_t* host_map, int64
 
 namespace bh {
 const uint8_t* surrogate_trust(const bh_surrogate* s) { return s && s->trusted ? s->trust : nullptr; }
+unsigned surrogate_version(const bh_surrogate* s) { return s ? s->version : 0u; }
 const void* surrogate_pack(const bh_surrogate* s) { return s ? s->pk : nullptr; }
 }  // namespace bh

@@ -131,6 +131,9 @@ def test_batch_argument_checks():
     assert L.bh_batch_create(reqs, 1, C.byref(o2), 0, C.byref(h)) == api.BH_ERR_UNSUPPORTED
     o3 = api.options(fixed_eps=0.5)
     assert L.bh_batch_create(reqs, 1, C.byref(o3), 0, C.byref(h)) == api.BH_ERR_UNSUPPORTED
+    o4 = api.options(collect_stats=1)
+    assert L.bh_batch_create(reqs, 1, C.byref(o4), 0, C.byref(h)) == api.BH_ERR_UNSUPPORTED
+    assert L.bh_last_stats(None, None) == api.BH_ERR_ARG
     assert L.bh_batch_launch(None, None) == api.BH_ERR_ARG
     assert L.bh_batch_destroy(None) == api.BH_OK
 

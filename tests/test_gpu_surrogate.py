@@ -242,6 +242,65 @@ def test_render_with_surrogate_matches_oracle(bh, trained, ref):
     assert s["max_angle"] <= 1e-4
 
 
+def test_batch_with_surrogate_equals_per_frame_renders(bh, trained):
+    """The surrogate inside a batch: the 16 orbit frames at 960x540 plus a
+    flat-space request and one with the sky at 500 M (neither may route to
+    the network) as one FP32 batch, two groups, graph and no graph: every
+    image equals bh_render of that request with the same network bit for
+    bit, the network served rays in the eligible frames (with an image sky a
+    pixel's colour follows its exit azimuth continuously, so served pixels
+    differ from the batch without the network), and after the network's
+    parameters change the batch refuses to launch."""
+    import torch
+    from dataclasses import replace
+    sur, _ = trained
+    tex = inputs.sky_texture(512, 256, seed=3)
+    frames = [inputs.shrink(f, 960, 540) for f in inputs.orbit_4k()]
+    frames = [replace(f, scene=replace(f.scene, sky_tex=tex)) for f in frames]
+    frames.append(inputs.Frame(inputs.Camera(40.0, 70.0, 10.0, 60.0, 96, 64),
+                               inputs.Scene(M=0.0, r_sky=1000.0, disk=(2.0, 12.0)), "flat"))
+    frames.append(replace(frames[3], scene=replace(frames[3].scene, r_sky=500.0 * frames[3].scene.M)))
+    opt = bh.options(precision=bh.FP32, batch_groups=2)
+    opt.surrogate = sur.handle
+    ref_imgs, served = [], 0
+    for f in frames:
+        o1 = bh.options(precision=bh.FP32)
+        o1.surrogate = sur.handle
+        img, _ = bh.render(f.camera, f.scene, o1)
+        torch.cuda.synchronize()
+        ref_imgs.append(img.cpu().numpy())
+        served += bh.last_counts()["surrogate"]
+    assert served > 10000
+    plain = bh.Batch(frames, bh.options(precision=bh.FP32, batch_groups=2), use_graph=False)
+    plain.launch()
+    torch.cuda.synchronize()
+    plain_imgs = [x.cpu().numpy() for x in plain.images]
+    plain.close()
+    for graph in (False, True):
+        b = bh.Batch(frames, opt, use_graph=graph)
+        b.launch()
+        b.launch()
+        torch.cuda.synchronize()
+        differ = 0
+        for k, (img, ref_img) in enumerate(zip(b.images, ref_imgs)):
+            np.testing.assert_array_equal(img.cpu().numpy(), ref_img, err_msg=f"request {k} graph {graph}")
+            differ += int((img.cpu().numpy() != plain_imgs[k]).any(axis=-1).sum())
+        # the last two requests do not route: identical to the batch without the network
+        for k in (len(frames) - 2, len(frames) - 1):
+            np.testing.assert_array_equal(b.images[k].cpu().numpy(), plain_imgs[k])
+        assert differ > 0.5 * served, (differ, served)
+        b.close()
+    # a batch keeps the network's parameter and trust version
+    b = bh.Batch(frames[:2], opt, use_graph=False)
+    params, m, v, trust = sur.get(0), sur.get(2), sur.get(3), sur.trust()
+    sur.set(params, m, v)
+    with pytest.raises(bh.BhError) as e:
+        b.launch()
+    assert e.value.status == bh.BH_ERR_STATE
+    b.close()
+    sur.set_trust(trust)
+
+
 def test_new_parameters_invalidate_the_trust_map(bh, trained):
     """A render routes rays to the network only while its trust map was
     built for the current parameters: after set_params or a training step
