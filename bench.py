@@ -214,6 +214,7 @@ def main() -> int:
         tot = 0
         per_path = {}
         split = {}
+        timeline = []
         opt_s = api.options(precision=opt.precision, rtol=opt.rtol, rtol_fp32=opt.rtol_fp32,
                             collect_stats=1)
         for f, buf in zip(frames, bufs):
@@ -226,6 +227,8 @@ def main() -> int:
             for k in ("accepted", "rejected", "newton", "capped"):
                 for q in ("fp64", "fp32"):
                     split[(k, q)] = split.get((k, q), 0) + st[k][q]
+            timeline.append(st["timeline_us"])
+        step_evals.timeline = timeline
         return tot, per_path, split
 
     def controller(split, per_path):
@@ -247,6 +250,10 @@ def main() -> int:
         return flop, ms / n, flop / (ms / n * 1e-3) / 1e12
 
     evals, paths, split = step_evals(opt_fast)
+    tl = step_evals.timeline
+
+    def tl_mean(key, q):
+        return round(sum(t[key][q] for t in tl) / len(tl), 1)
     flop_launch, avg_launch_ms, achieved = roof(evals, tim, args.steps)
     _, avg_launch_frames, achieved_frames = roof(evals, tim_frames, args.steps)
     if tim64 is not None:
@@ -286,6 +293,13 @@ def main() -> int:
                               "ms_per_step": round(ms_frames, 4),
                               "integrator_avg_launch_ms": round(avg_launch_frames, 4),
                               "integrator_tflops": round(achieved_frames, 3),
+                              "queue_timeline_us": {
+                                  "note": "one frame's main queue (instrumented pass), mean over the "
+                                          "frames: when wavefronts found the queue dry and left it",
+                                  "dry_first": tl_mean("queue_dry_us", 0),
+                                  "dry_median": tl_mean("queue_dry_us", 1),
+                                  "exit_median": tl_mean("wave_exit_us", 1),
+                                  "exit_last": tl_mean("wave_exit_us", 2)},
                               "kernels_ms_per_step": {k: round(v[0] / args.steps, 4)
                                                       for k, v in tim_frames.items()}},
         "fp64_plain": {"value": round(value64, 2), "unit": "Mrays/s",

@@ -224,6 +224,16 @@ typedef struct {
                                 integrator (capture logit not negative)                 */
     int64_t sur_untrusted;   /* rays eligible for the surrogate whose trust-map bin is
                                 not trusted (they stay on the integrator)              */
+    /* Queue timeline of a bh_render (0 waves for bh_trace_rays): per wavefront
+     * of the main queue (FP32 rays in FP32 mode, all rays in FP64 mode), the
+     * times at which it entered the queue, found it dry and left it, in
+     * microseconds after the first wavefront entered; min, median and max
+     * over the wavefronts.  (The blocks that first drain FP32 mode's critical
+     * band enter the main queue late.) */
+    int64_t timeline_waves;
+    double  wave_enter_us[3];
+    double  queue_dry_us[3];
+    double  wave_exit_us[3];
 } bh_stats;
 
 /* Copies the statistics of the last call on this device into *st and

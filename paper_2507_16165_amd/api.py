@@ -52,7 +52,9 @@ class Stats(C.Structure):
                 ("step_evals", C.c_int64), ("accepted", C.c_int64 * 2),
                 ("rejected", C.c_int64 * 2), ("newton", C.c_int64 * 2),
                 ("capped", C.c_int64 * 2), ("sur_listed", C.c_int64),
-                ("sur_fallback", C.c_int64), ("sur_untrusted", C.c_int64)]
+                ("sur_fallback", C.c_int64), ("sur_untrusted", C.c_int64),
+                ("timeline_waves", C.c_int64), ("wave_enter_us", C.c_double * 3),
+                ("queue_dry_us", C.c_double * 3), ("wave_exit_us", C.c_double * 3)]
 
 
 class Request(C.Structure):
@@ -293,7 +295,10 @@ def last_stats(stream=None) -> dict:
             "path": dict(zip(("none", "fp64", "fp32", "surrogate"), (int(x) for x in s.path))),
             "step_evals": s.step_evals, "accepted": pair(s.accepted), "rejected": pair(s.rejected),
             "newton": pair(s.newton), "capped": pair(s.capped), "sur_listed": s.sur_listed,
-            "sur_fallback": s.sur_fallback, "sur_untrusted": s.sur_untrusted}
+            "sur_fallback": s.sur_fallback, "sur_untrusted": s.sur_untrusted,
+            "timeline_waves": s.timeline_waves,
+            "timeline_us": {k: [round(x, 2) for x in getattr(s, k)]
+                            for k in ("wave_enter_us", "queue_dry_us", "wave_exit_us")}}
 
 
 KERNEL_CLASSES = ("setup", "integrate", "shade", "surrogate")

@@ -46,6 +46,8 @@ struct Workspace {
     unsigned long long* counts = nullptr;  // 32 counters: bh_last_counts, bh_last_stats
     int64_t last_n = 0;
     bool last_stats = false;               // the last call collected statistics
+    int last_tl_waves = 0;                 // ... and the size of its queue timeline
+    double clock_hz = 1e8;                 // device wall clock (queue timeline)
     int cus = 0;
 };
 
@@ -135,6 +137,9 @@ bh_status get_workspace(int64_t n, hipStream_t stream, Workspace** out) {
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
         ws.cus = cus > 0 ? cus : 256;
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            ws.clock_hz = 1e3 * khz;
     }
     if (n > ws.cap || ws.base == nullptr) {
         int64_t cap = n > 4096 ? n : 4096;
@@ -416,11 +421,20 @@ bh_status run(const bh::Source& src, bool explicit_u0, double u0_uniform, const 
     Workspace* ws = nullptr;
     bh_status st = get_workspace(src.n, stream, &ws);
     if (st != BH_OK) return st;
-    st = run_on(ws->w, ws->cus, src, explicit_u0, u0_uniform, scene, opt, rgba, out, stream,
+    bh::Work w = ws->w;
+    if (opt->collect_stats && !explicit_u0) {
+        // the queue timeline goes to the explicit-ray u0 array, unused here
+        w.tl = reinterpret_cast<unsigned long long*>(ws->w.u0);
+        w.tl_waves = (int)std::min<int64_t>(bh::kTimelineWaves, ws->cap / 3);
+        hipError_t e = bh::launch_zero(w.tl, 3 * (int64_t)w.tl_waves, stream);
+        if (e != hipSuccess) return hip_fail(e, "timeline");
+    }
+    st = run_on(w, ws->cus, src, explicit_u0, u0_uniform, scene, opt, rgba, out, stream,
                 samples_side, true);
     if (st == BH_OK) {
         ws->last_n = src.n;
         ws->last_stats = opt->collect_stats != 0;
+        ws->last_tl_waves = w.tl ? w.tl_waves : 0;
     }
     return st;
 }
@@ -640,6 +654,29 @@ bh_status bh_last_stats(bh_stats* st, void* stream) {
     st->sur_listed = listed;
     st->sur_fallback = listed - st->path[BH_PATH_SURROGATE];
     st->sur_untrusted = (int64_t)c[8];
+    if (ws->last_tl_waves > 0) {
+        std::vector<unsigned long long> tl(3 * (size_t)ws->last_tl_waves);
+        e = hipMemcpy(tl.data(), ws->w.u0, sizeof(unsigned long long) * tl.size(),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "reading the queue timeline");
+        std::vector<double> t[3];
+        unsigned long long t0 = ~0ull;
+        for (int k = 0; k < ws->last_tl_waves; ++k)
+            if (tl[3 * k]) t0 = std::min(t0, tl[3 * k]);
+        for (int k = 0; k < ws->last_tl_waves; ++k) {
+            if (!tl[3 * k]) continue;  // a wavefront of the band only, or not launched
+            for (int q = 0; q < 3; ++q)
+                t[q].push_back(tl[3 * k + q] >= t0 ? 1e6 * (double)(tl[3 * k + q] - t0) / ws->clock_hz : 0.0);
+        }
+        st->timeline_waves = (int64_t)t[0].size();
+        double* dst[3] = {st->wave_enter_us, st->queue_dry_us, st->wave_exit_us};
+        for (int q = 0; q < 3 && !t[q].empty(); ++q) {
+            std::sort(t[q].begin(), t[q].end());
+            dst[q][0] = t[q].front();
+            dst[q][1] = t[q][t[q].size() / 2];
+            dst[q][2] = t[q].back();
+        }
+    }
     return BH_OK;
 }
 

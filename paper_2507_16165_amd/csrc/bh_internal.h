@@ -119,7 +119,14 @@ struct Work {
     int32_t* q64;             // FP64 band queue (FP32 mode): ray indices ...
     double2* q64rec;          // ... and their start records
     int32_t* ctr;             // queue counters, kCtrInts ints (layout below)
+    // statistics runs of single renders: per main-queue wavefront (index
+    // block * 4 + wave) the device-clock times at which it entered the queue,
+    // found it dry and left it (3 values, zeroed before the launch; tl_waves
+    // entries); NULL otherwise
+    unsigned long long* tl;
+    int tl_waves;
 };
+constexpr int kTimelineWaves = 1 << 16;   // timeline capacity in wavefronts
 
 // Queue counters (int32 indices into Work::ctr); each head sits on its own
 // 256-byte line.
@@ -246,6 +253,7 @@ hipError_t launch_integrate(int64_t n, bool explicit_u0, double u0_uniform, cons
                             const DevTol& tol, int precision, const Work& w, int cus,
                             int grid_blocks, int chunk, bool stats, hipStream_t s);
 hipError_t launch_stats(int64_t n, const Work& w, unsigned long long* out, hipStream_t s);
+hipError_t launch_zero(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
                         const Out& out, int precision, hipStream_t s);
 hipError_t launch_shade_samples(const Source& src, const DevScene& sc, const Work& w, float* rgba,

@@ -678,8 +678,11 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     int cnext = 0, cend = 0;
     bool drained = false;
     int slice = (int)(blockIdx.x % (unsigned)nslices), dry = 0;
-    // per-lane statistics over all its rays (STATS only)
+    // per-lane statistics over all its rays (STATS only), and the
+    // wavefront's queue timeline (main queues of single renders)
     int n_acc = 0, n_rej = 0, n_newt = 0, n_cap = 0;
+    unsigned long long t_enter = 0, t_dry = 0;
+    if constexpr (STATS && VIRTUAL) t_enter = wall_clock64();
 
     for (;;) {
         // ---- (A) idle lanes start their prefetched rays, once at least
@@ -748,7 +751,18 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // dry.  (A wavefront with no active lane otherwise runs one step with
         // every lane masked off, at its start and while the queue drains;
         // the loop keeps a single back edge.)
+        if constexpr (STATS && VIRTUAL) {
+            if (drained && t_dry == 0) t_dry = wall_clock64();
+        }
         if (drained && cnext >= cend && __ballot(active || pf_valid) == 0) {
+            if constexpr (STATS && VIRTUAL) {
+                const int wid = (int)(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
+                if (a.w.tl && wid < a.w.tl_waves && lane == 0) {
+                    a.w.tl[3 * wid] = t_enter;
+                    a.w.tl[3 * wid + 1] = t_dry;
+                    a.w.tl[3 * wid + 2] = wall_clock64();
+                }
+            }
             if constexpr (STATS) {
                 // one atomic per counter and wavefront
                 unsigned long long* st =
@@ -1563,6 +1577,21 @@ hipError_t launch_integrate_paper(int64_t n, bool explicit_u0, double u0_uniform
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g > (int64_t)cus * 16) g = (int64_t)cus * 16;
     k_integrate_paper<<<(unsigned)g, kBlock, 0, s>>>(a, eps);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(unsigned long long* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = 0;
+}
+
+// Zeroes n 64-bit words with a kernel (not a memset, so a caller may capture it).
+hipError_t launch_zero(unsigned long long* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    unsigned g = blocks_for(n);
+    if (g > 1024) g = 1024;
+    k_zero<<<g, kBlock, 0, s>>>(p, n);
     return hipGetLastError();
 }
 

@@ -292,8 +292,15 @@ def test_stats_account_for_every_ray_and_step(bh, ref, precision):
         oa, orj = int(r.n_acc[integ].sum()), int(r.n_rej[integ].sum())
         assert abs(st["accepted"]["fp64"] / oa - 1.0) < 0.02, (st["accepted"], oa)
         assert abs(st["rejected"]["fp64"] - orj) <= 0.02 * oa, (st["rejected"], orj)
+    # queue timeline: every main-queue wavefront entered, found the queue dry
+    # and left, in that order
+    tl = st["timeline_us"]
+    assert st["timeline_waves"] > 0
+    assert tl["wave_enter_us"][0] == 0.0
+    for q in range(3):
+        assert tl["wave_enter_us"][q] <= tl["queue_dry_us"][q] <= tl["wave_exit_us"][q], tl
     print(f"{precision}: accepted {st['accepted']}, rejected {st['rejected']}, "
-          f"newton {st['newton']} over {integrated} integrated rays")
+          f"newton {st['newton']} over {integrated} integrated rays; timeline {tl}")
 
 
 def test_counts(bh):
