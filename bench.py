@@ -725,7 +725,22 @@ def batch_leg(args, api, torch):
     wall_ms = (time.perf_counter() - t0) * 1e3 / args.batch_reps
     med = sorted(runs, key=lambda r: r["makespan_ms"])[len(runs) // 2]
     b.close()
+    # the same requests as one group: a single persistent integrator launch
+    # over all 512 requests (set-up, integration and shading once each)
+    one = dict(best, batch_groups=1)
+    b1 = api.Batch(frames, autotune.options_for(one, api.FP32), use_graph=True)
+    b1.launch()
+    torch.cuda.synchronize()
+    runs1 = []
+    for _ in range(args.batch_reps):
+        b1.launch()
+        runs1.append(b1.stats())
+    med1 = sorted(runs1, key=lambda r: r["makespan_ms"])[len(runs1) // 2]
+    b1.close()
     return {"requests": med["requests"], "rays": med["rays"], "graph": True,
+            "one_launch": {"mrays_per_s": round(med1["mrays_per_s"], 2),
+                           "makespan_ms": round(med1["makespan_ms"], 3),
+                           "p50_ms": round(med1["p50_ms"], 3), "p99_ms": round(med1["p99_ms"], 3)},
             "autotuned": {k: best[k] for k in ("grid_blocks", "chunk", "refill", "batch_groups",
                                                 "candidates_timed")},
             "mrays_per_s": round(med["mrays_per_s"], 2), "makespan_ms": round(med["makespan_ms"], 3),
