@@ -649,7 +649,7 @@ template <typename T, bool VIRTUAL, bool BATCH, bool R32, bool KAPPA, bool STATS
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
                           int nslices, T rtol, T ntol, const BatchConst* __restrict__ bct,
-                          int refill_min) {
+                          int refill_min, int qblocks) {
     const int lane = lane_id();
     // constants in the scaled variable v = s u (s = 3M; s = 1, k = 0 for
     // M = 0): wave-uniform for one frame, per lane for a batch
@@ -678,6 +678,17 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     int cnext = 0, cend = 0;
     bool drained = false;
     int slice = (int)(blockIdx.x % (unsigned)nslices), dry = 0;
+    // Single renders: a wavefront's first chunk in its block's slice is
+    // assigned without an atomic.  The slice's first chunks go to the
+    // wavefronts of its blocks in block order (W of them, qblocks blocks take
+    // part in the queue); the head counter hands out chunks W, W + 1, ...
+    // (one-frame launches spend a larger share of their time starting up:
+    // 3% less per-frame integration; batches measured 1% slower with it)
+    constexpr int kWavesPerBlock = kBlock / kWave;
+    int first_k = -1;
+    if constexpr (!BATCH)
+        first_k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x / (unsigned)nslices) * kWavesPerBlock +
+                                                 (int)(threadIdx.x >> 6));
     // per-lane statistics over all its rays (STATS only), and the
     // wavefront's queue timeline (main queues of single renders)
     int n_acc = 0, n_rej = 0, n_newt = 0, n_cap = 0;
@@ -718,10 +729,20 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             // starts on its block's slice and moves on when a slice is dry.
             while (cnext >= cend && !drained) {
                 int k = 0;
-                if (lane == 0) k = atomicAdd(&heads[slice * kCtrStride], 1);
-                // lane 0's value, read into a scalar register: the chunk
-                // bounds derived from it stay wave-uniform (scalar ALU)
-                k = __builtin_amdgcn_readlane(k, 0);
+                if (first_k >= 0) {
+                    k = first_k;
+                    first_k = -1;
+                } else {
+                    if (lane == 0) k = atomicAdd(&heads[slice * kCtrStride], 1);
+                    // lane 0's value, read into a scalar register: the chunk
+                    // bounds derived from it stay wave-uniform (scalar ALU)
+                    k = __builtin_amdgcn_readlane(k, 0);
+                    if constexpr (!BATCH) {
+                        const int wslice =
+                            slice < qblocks ? (qblocks - slice + nslices - 1) / nslices : 0;
+                        k += wslice * kWavesPerBlock;
+                    }
+                }
                 const int64_t base = ((int64_t)k * nslices + slice) * a.chunk;
                 if (k >= 0 && base < total) {
                     cnext = (int)base;
@@ -909,7 +930,7 @@ __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     run_queue<double, true, BATCH, false, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
                                                  kSlices, a.tol.rtol64, a.tol.newton64, bct,
-                                                 a.tol.refill64);
+                                                 a.tol.refill64, (int)gridDim.x);
 }
 
 // FP32 mode (batches keep FP32 records).  The first `band_blocks` blocks
@@ -927,12 +948,13 @@ __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_bloc
         ab.chunk = 64;
         run_queue<double, false, BATCH, BATCH, KAPPA, STATS>(ab, a.w.q64, a.w.q64rec,
                                                       a.w.ctr[kCtrBandSize], &a.w.ctr[kCtrBand], 1,
-                                                      a.tol.rtol64, a.tol.newton64, bct, 1);
+                                                      a.tol.rtol64, a.tol.newton64, bct, 1,
+                                                      band_blocks);
         __builtin_amdgcn_s_setprio(0);
     }
     run_queue<float, true, BATCH, BATCH, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
                                                 kSlices, a.tol.rtol32, a.tol.newton32, bct,
-                                                a.tol.refill32);
+                                                a.tol.refill32, (int)gridDim.x);
 }
 
 template <bool KAPPA, bool STATS>
