@@ -198,3 +198,29 @@ def test_render_noalloc_rejects_frames_beyond_its_workspace():
     assert "photon sphere" in L.bh_last_error().decode()
     assert call(inputs.Camera(30, 90, 0, 60, 8, 8), rgba=0) == api.BH_ERR_ARG
     assert L.bh_render_noalloc(None, None, None, None, None, None) == api.BH_ERR_ARG
+
+
+def test_size_limits_are_checked_before_any_device_call():
+    """Frames, sample grids, ray counts and batches beyond the 32-bit ray
+    index the kernels use are refused with BH_ERR_ARG (no device needed)."""
+    L = api.lib()
+    sc = api.scene_struct(inputs.Scene(M=1.0))
+    o = api.options()
+    big = api.camera_struct(inputs.Camera(30, 90, 0, 60, 65536, 32768))   # 2^31 pixels
+    assert L.bh_render(C.byref(big), C.byref(sc), C.byref(o), C.c_void_p(1), None, None) == api.BH_ERR_ARG
+    assert "2^31" in L.bh_last_error().decode()
+    cam = api.camera_struct(inputs.Camera(30, 90, 0, 60, 16384, 16384))   # 2^28 pixels x 16 samples
+    o16 = api.options(samples_side=4)
+    assert L.bh_render(C.byref(cam), C.byref(sc), C.byref(o16), C.c_void_p(1), None, None) == api.BH_ERR_ARG
+    assert "samples" in L.bh_last_error().decode()
+    out = api.RayOut()
+    out.cls = 1
+    assert L.bh_trace_rays(C.c_void_p(1), C.c_void_p(1), 1 << 31, C.byref(sc), C.byref(o),
+                           C.byref(out), None) == api.BH_ERR_ARG
+    assert L.bh_reserve(-1) == api.BH_ERR_ARG and L.bh_reserve(1 << 31) == api.BH_ERR_ARG
+    reqs = (api.Request * 2)()
+    for k in range(2):
+        reqs[k] = api.Request(api.camera_struct(inputs.Camera(30, 90, 0, 60, 32768, 32768)), sc, 1)
+    h = C.c_void_p()
+    assert L.bh_batch_create(reqs, 2, C.byref(o), 0, C.byref(h)) == api.BH_ERR_ARG
+    assert "2^31" in L.bh_last_error().decode()
