@@ -301,6 +301,50 @@ def test_batch_with_surrogate_equals_per_frame_renders(bh, trained):
     sur.set_trust(trust)
 
 
+def test_checkpoint_round_trip_resumes_training_and_rendering(bh, trained, rand_params, tmp_path):
+    """surrogate.save / load: parameters, Adam moments, step count and trust
+    map come back exactly.  Training resumed from the checkpoint takes the
+    same next step as the original network (bit for bit), and a render with
+    the loaded network equals one with the trained network."""
+    import torch
+    from paper_2507_16165_amd import surrogate as S
+    a = bh.Surrogate(rand_params, max_batch=1024)
+    b_, r0 = _batch(512, 11)
+    esc = b_ > B_CRIT
+    phi = np.where(esc, R.predict_exit(b_, r0, np.zeros(b_.size)), np.nan)
+    cap = (~esc).astype(np.uint8)
+    for _ in range(3):
+        a.train_step(_t(b_), _t(r0), _t(phi), _t(cap), 1e-3)
+    torch.cuda.synchronize()
+    S.save(a, str(tmp_path / "ck.npz"), step=3)
+    c = S.load(str(tmp_path / "ck.npz"), max_batch=1024)
+    for k in (0, 2, 3):
+        np.testing.assert_array_equal(c.get(k), a.get(k))
+    a.train_step(_t(b_), _t(r0), _t(phi), _t(cap), 1e-3)
+    c.train_step(_t(b_), _t(r0), _t(phi), _t(cap), 1e-3)
+    torch.cuda.synchronize()
+    for k in (0, 1, 2, 3):
+        np.testing.assert_array_equal(c.get(k), a.get(k))
+    a.close()
+    c.close()
+    sur, _ = trained
+    S.save(sur, str(tmp_path / "trained.npz"))
+    d = S.load(str(tmp_path / "trained.npz"))
+    np.testing.assert_array_equal(d.trust(), sur.trust())
+    f = inputs.shrink(max(inputs.orbit_4k(), key=lambda fr: fr.camera.r / fr.scene.M), 960, 540)
+    imgs, counts = [], []
+    for net in (sur, d):
+        opt = bh.options(precision=bh.FP32)
+        opt.surrogate = net.handle
+        img, _ = bh.render(f.camera, f.scene, opt)
+        torch.cuda.synchronize()
+        imgs.append(img.cpu().numpy())
+        counts.append(bh.last_counts()["surrogate"])
+    assert counts[0] == counts[1] > 0
+    np.testing.assert_array_equal(imgs[0], imgs[1])
+    d.close()
+
+
 def test_new_parameters_invalidate_the_trust_map(bh, trained):
     """A render routes rays to the network only while its trust map was
     built for the current parameters: after set_params or a training step
