@@ -886,12 +886,12 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                                 : capture        ? CAPTURED
                                                  : SKY;
             const double pe = (double)(sky_done ? phi + hh_new : (capped ? phi : phin));
-            // r = 1/u = s/v: FP32 rays take the hardware reciprocal (1 ulp, far
-            // below their integration error), FP64 rays a correctly rounded
-            // division
-            const double rh = !disk_hit                ? 0.0
-                              : sizeof(T) == 4 ? (double)(s * recip(vn))
-                                               : (double)s / (double)vn;
+            // r = 1/u = s/v from the reciprocal: the hardware estimate for FP32
+            // rays (1 ulp), refined by one Newton step for FP64 rays (the
+            // step squares the estimate's relative error, which leaves it far
+            // below their integration error; an IEEE division here cost
+            // about ten instructions in the block every finishing ray runs)
+            const double rh = !disk_hit ? 0.0 : (double)(s * recip(vn));
             if (R32) a.w.res32[id] = make_float2((float)pe, (float)rh);
             else a.w.res[id] = make_double2(pe, rh);
             // Step evaluations: the trial steps, plus the Newton re-steps of a
