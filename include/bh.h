@@ -110,7 +110,9 @@ typedef struct {
     int    analytic_capture; /* 1: with no disk, an ingoing ray with b below the band is
                                 classified CAPTURED without integration (exact: the
                                 effective potential peaks at b = 3 sqrt(3) M)          */
-    int    grid_blocks;      /* persistent integrator grid, 256-thread blocks; 0 = auto */
+    int    grid_blocks;      /* persistent integrator grid, 256-thread blocks; 0 = auto
+                                (single renders and traces: 3/4 of the resident
+                                blocks; batches: all resident blocks)               */
     int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto  */
     int    samples_side;     /* bh_render: n x n rays per pixel at the stratified
                                 sub-pixel centres, averaged (box filter); 0 or 1 =
