@@ -382,6 +382,20 @@ bh_status run_on(const bh::Work& ws_w, int cus, const bh::Source& src, bool expl
     }
     bh::Work w = ws_w;
     if (!explicit_u0) w.u0 = nullptr;
+    // An FP32 camera render that returns only the image keeps its start and
+    // result records in FP32, in the FP64 records' memory, as FP32 batches
+    // do: set-up writes, the integrator reads and writes, and shading reads
+    // 16 bytes per ray fewer, for the same pixels (FP32 shading rounds its
+    // inputs to float either way).  Per-ray outputs, the surrogate,
+    // samples per pixel and the fixed-step mode keep the FP64 records.
+    const bh::Out dout = dev_out(out);
+    const bool any_out = dout.cls || dout.b || dout.phi_end || dout.exit_dir || dout.r_hit ||
+                         dout.steps || dout.path;
+    if (opt->precision == BH_FP32 && !explicit_u0 && !any_out && !sur_pack &&
+        !(opt->fixed_eps > 0.0) && samples_side == 1) {
+        w.rec32 = reinterpret_cast<float2*>(w.rec);
+        w.res32 = reinterpret_cast<float2*>(w.res);
+    }
     const bool stats = opt->collect_stats != 0;
     if (stats) rt.stats = reinterpret_cast<unsigned long long*>(w.ctr + bh::kCtrStats);
     hipError_t e = bh::launch_reset(w.ctr, stream);

@@ -104,12 +104,13 @@ struct DevRoute {
 struct Work {
     double* u0;               // 1/|origin| per ray (explicit-ray mode only)
     double2* rec;             // start record {w0, phi1}; w0 = NaN: not in the main queue
-    // FP32-mode batches: the start record as {w0, phi1} in FP32, the FP32
-    // integrator's inputs, in rec's memory; NULL otherwise
+    // FP32-mode batches, and FP32 camera renders that return only the image:
+    // the start record as {w0, phi1} in FP32, the FP32 integrator's inputs,
+    // in rec's memory; NULL otherwise
     float2* rec32;
     double2* res;             // result record {phi_end, r_hit}
-    // FP32-mode batches (images only): the result record as {phi_end, r_hit}
-    // in FP32, the FP32 shading's inputs, in res's memory; NULL otherwise
+    // set together with rec32: the result record as {phi_end, r_hit} in FP32,
+    // the FP32 shading's inputs, in res's memory; NULL otherwise
     float2* res32;
     int32_t* qsur;            // surrogate list (kSurSlices slices): ray indices ...
     double2* qsurrec;         // ... and {b, w0}

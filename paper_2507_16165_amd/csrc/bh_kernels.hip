@@ -367,6 +367,10 @@ __device__ __forceinline__ void append_sur(bool to_sur, int64_t i, double b, dou
     }
 }
 
+// R32: FP32 records (w.rec32 / w.res32), for FP32 camera renders that return
+// only the image; the FP32 integrator and shading then read them as batches
+// do.
+template <bool R32>
 __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRoute rt, Work w,
                                                   double* out_b) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -374,9 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_setup(Source src, DevScene sc, DevRo
     double b = 0.0, w0 = 0.0, phi1 = 0.0;
     if (i < src.n) {
         if (!src.origin && rt.precision == 1 && !rt.trust)
-            to = setup_camera32<false, false>(src.cam, sc, rt, i, i, w, out_b, b, w0, phi1);
+            to = setup_camera32<false, R32>(src.cam, sc, rt, i, i, w, out_b, b, w0, phi1);
         else
-            to = setup_ray(source_basis(src, i, sc.M, sc.r_sky), sc, rt, i, w, out_b, b, w0, phi1);
+            to = setup_ray<false, R32>(source_basis(src, i, sc.M, sc.r_sky), sc, rt, i, w, out_b,
+                                       b, w0, phi1);
     }
     append_band(to == kToBand, i, w0, phi1, w);
     if (rt.trust) append_sur(to == kToSur, i, b, w0, src.n, w);
@@ -939,20 +944,20 @@ __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
 // latency-bound; their waves start with the launch and run at raised issue
 // priority, so the FP32 waves sharing their SIMDs fill the gaps and the band
 // ends inside the FP32 work instead of trailing it.
-template <bool BATCH, bool KAPPA, bool STATS = false>
+template <bool BATCH, bool R32, bool KAPPA, bool STATS = false>
 __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_blocks) {
     const BatchConst* bct = stage_consts<BATCH>(a);
     if ((int)blockIdx.x < band_blocks) {
         __builtin_amdgcn_s_setprio(3);
         IntegArgs ab = a;
         ab.chunk = 64;
-        run_queue<double, false, BATCH, BATCH, KAPPA, STATS>(ab, a.w.q64, a.w.q64rec,
+        run_queue<double, false, BATCH, R32, KAPPA, STATS>(ab, a.w.q64, a.w.q64rec,
                                                       a.w.ctr[kCtrBandSize], &a.w.ctr[kCtrBand], 1,
                                                       a.tol.rtol64, a.tol.newton64, bct, 1,
                                                       band_blocks);
         __builtin_amdgcn_s_setprio(0);
     }
-    run_queue<float, true, BATCH, BATCH, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
+    run_queue<float, true, BATCH, R32, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
                                                 kSlices, a.tol.rtol32, a.tol.newton32, bct,
                                                 a.tol.refill32, (int)gridDim.x);
 }
@@ -964,10 +969,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntegArgs a) {
 
 // Held to 64 VGPRs (8 waves per SIMD for the FP32 rays); the FP64 band code
 // spills a few registers, which only band waves pay.
-template <bool KAPPA, bool STATS>
+template <bool KAPPA, bool STATS, bool R32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
 k_integrate_fp32(IntegArgs a, int band_blocks) {
-    integrate_fp32<false, KAPPA, STATS>(a, band_blocks);
+    integrate_fp32<false, R32, KAPPA, STATS>(a, band_blocks);
 }
 
 // Batch kernels: per-request constants come from LDS.
@@ -979,7 +984,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64_batch(IntegArgs a) {
 template <bool KAPPA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void
 k_integrate_fp32_batch(IntegArgs a, int band_blocks) {
-    integrate_fp32<true, KAPPA>(a, band_blocks);
+    integrate_fp32<true, true, KAPPA>(a, band_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1275,13 +1280,14 @@ __device__ __forceinline__ void shade_ray(const Basis& B, const DevScene& sc, co
     }
 }
 
-template <bool F32>
+// R32 (with F32): the result records are FP32 (w.res32).
+template <bool F32, bool R32 = false>
 __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work w, float* rgba,
                                                   Out out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= src.n) return;
     float4* px = rgba ? reinterpret_cast<float4*>(rgba) + i : nullptr;
-    if (F32) shade_ray32(source_basis32(src, i), sc, w, i, px, out, i);
+    if (F32) shade_ray32<R32>(source_basis32(src, i), sc, w, i, px, out, i);
     else shade_ray(source_basis(src, i, sc.M, sc.r_sky), sc, w, i, px, out, i);
 }
 
@@ -1419,7 +1425,8 @@ hipError_t launch_reset(int32_t* ctr, hipStream_t s) {
 hipError_t launch_setup(const Source& src, const DevScene& sc, const DevRoute& rt, const Work& w,
                         double* out_b, hipStream_t s) {
     if (src.n == 0) return hipSuccess;
-    k_setup<<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, rt, w, out_b);
+    if (w.rec32) k_setup<true><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, rt, w, out_b);
+    else k_setup<false><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, rt, w, out_b);
     return hipGetLastError();
 }
 
@@ -1461,19 +1468,28 @@ static unsigned persistent_grid(int64_t n, int cus, int per_cu, int grid_blocks)
 // and keep that.
 static int single_render_blocks(int per_cu) { return per_cu > 1 ? per_cu - per_cu / 4 : 1; }
 
+template <bool KAPPA, bool STATS, bool R32>
+static void launch_integrate32_k(const IntegArgs& a, int cus, int grid_blocks, hipStream_t s) {
+    static int occ = 0;  // per variant
+    const int per_cu = blocks_per_cu(k_integrate_fp32<KAPPA, STATS, R32>, &occ);
+    const unsigned g = persistent_grid(a.n, cus, single_render_blocks(per_cu), grid_blocks);
+    const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
+    k_integrate_fp32<KAPPA, STATS, R32><<<g, kBlock, 0, s>>>(a, band_blocks);
+}
+
+// FP32 records (a.w.rec32 set by the caller) or FP64 ones.
 template <bool KAPPA, bool STATS>
 static void launch_integrate_k(const IntegArgs& a, int precision, int cus, int grid_blocks,
                                hipStream_t s) {
-    static int occ64 = 0, occ32 = 0;  // per variant
+    static int occ64 = 0;  // per variant
     if (precision != 1) {
         const int per_cu = blocks_per_cu(k_integrate_fp64<KAPPA, STATS>, &occ64);
         const unsigned g = persistent_grid(a.n, cus, single_render_blocks(per_cu), grid_blocks);
         k_integrate_fp64<KAPPA, STATS><<<g, kBlock, 0, s>>>(a);
+    } else if (a.w.rec32) {
+        launch_integrate32_k<KAPPA, STATS, true>(a, cus, grid_blocks, s);
     } else {
-        const int per_cu = blocks_per_cu(k_integrate_fp32<KAPPA, STATS>, &occ32);
-        const unsigned g = persistent_grid(a.n, cus, single_render_blocks(per_cu), grid_blocks);
-        const int band_blocks = (int)min((unsigned)(cus >= 4 ? cus / 4 : 1), g);
-        k_integrate_fp32<KAPPA, STATS><<<g, kBlock, 0, s>>>(a, band_blocks);
+        launch_integrate32_k<KAPPA, STATS, false>(a, cus, grid_blocks, s);
     }
 }
 
@@ -1578,7 +1594,10 @@ hipError_t launch_batch_shade(const BatchDev& b, const Work& w, int precision, i
 hipError_t launch_shade(const Source& src, const DevScene& sc, const Work& w, float* rgba,
                         const Out& out, int precision, hipStream_t s) {
     if (src.n == 0) return hipSuccess;
-    if (precision == 1) k_shade<true><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
+    if (precision == 1 && w.res32)
+        k_shade<true, true><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
+    else if (precision == 1)
+        k_shade<true><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
     else k_shade<false><<<blocks_for(src.n), kBlock, 0, s>>>(src, sc, w, rgba, out);
     return hipGetLastError();
 }

@@ -137,6 +137,25 @@ def test_batch_edge_requests_equal_single_renders(bh, precision, graph):
     b.close()
 
 
+def test_image_only_fp32_renders_equal_renders_with_outputs(bh):
+    """An FP32 render that returns only the image keeps FP32 start and result
+    records (as FP32 batches do); one that also returns per-pixel outputs keeps
+    FP64 records.  The pixels must be the same bit for bit: ragged and 1x1
+    frames, disks, sky images, flat space, distant and close cameras, with and
+    without the per-call statistics (the instrumented integrator)."""
+    import torch
+    frames = mixed_frames() + edge_frames()
+    for stats in (0, 1):
+        opt = bh.options(precision=bh.FP32, collect_stats=stats)
+        for f in frames:
+            img, _ = bh.render(f.camera, f.scene, opt)
+            ref, out = bh.render(f.camera, f.scene, opt, fields=("cls",))
+            torch.cuda.synchronize()
+            assert out is not None and "cls" in out
+            np.testing.assert_array_equal(img.cpu().numpy(), ref.cpu().numpy(),
+                                          err_msg=f"{f.name} stats={stats}")
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_groups(bh, graph):
     """Requests split into up to 3 consecutive groups traced one after another:
