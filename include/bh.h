@@ -279,7 +279,11 @@ typedef struct bh_batch bh_batch;
  * and per-ray workspace (~60 bytes per ray, ~20 more with the surrogate), and
  * with use_graph != 0 captures the launch sequence into a hipGraph.  The
  * request array is copied; the output pointers are kept.  samples_side > 1,
- * fixed_eps > 0 and collect_stats are BH_ERR_UNSUPPORTED.  Synchronous. */
+ * fixed_eps > 0 and collect_stats are BH_ERR_UNSUPPORTED.  Each request group
+ * stages its requests' integrator constants in one block's LDS (32 bytes per
+ * request in FP32 batches, 64 in FP64 ones; about 5000 and 2500 requests per
+ * group with 160 KiB): a larger group is BH_ERR_ARG (use more batch_groups).
+ * Synchronous. */
 bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, int use_graph,
                           bh_batch** out);
 /* Enqueues one execution of the batch on `stream`. */

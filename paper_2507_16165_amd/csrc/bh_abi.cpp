@@ -841,6 +841,24 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
                  sz1 = align256((size_t)N), szc = align256(sizeof(int32_t) * bh::kCtrInts);
     const std::vector<int> gr = make_groups(off, opt->batch_groups);
     const int G = (int)gr.size() - 1;
+    // A group's integrator stages its requests' constants in LDS (32 bytes
+    // per request in FP32 batches, 64 in FP64 ones), its set-up and shading
+    // the request offsets (8 bytes each): a group's tables must fit one
+    // block's LDS.
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) !=
+            hipSuccess || lds_max <= 0)
+        lds_max = 65536;
+    const size_t per_req =
+        opt->precision == BH_FP32 ? sizeof(bh::Consts32) : sizeof(bh::Consts64);
+    for (int g = 0; g < G; ++g) {
+        const size_t ng = (size_t)(gr[g + 1] - gr[g]);
+        if (per_req * ng > (size_t)lds_max || 8 * (ng + 1) > (size_t)lds_max)
+            return cleanup(fail(BH_ERR_ARG,
+                                "request group %d holds %zu requests, more than one block's LDS "
+                                "(%d bytes) has room for; use more batch_groups",
+                                g, ng, lds_max));
+    }
     // per group: its requests' offsets relative to the group's first ray
     std::vector<int64_t> goff;
     for (int g = 0; g < G; ++g)

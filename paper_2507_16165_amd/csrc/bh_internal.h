@@ -187,6 +187,13 @@ struct BatchConst {
     float s32, v032, vsky32, vrin32, vrout32, vh32, atol32, k32;  // FP32 rays
 };
 
+// A request's constants in one precision: the per-request tables that batch
+// integrators stage in LDS (32 bytes per request for FP32 batches, 64 for
+// FP64 ones, instead of the 96 of BatchConst: a table of hundreds of
+// requests then leaves room for all resident blocks).
+struct Consts32 { float s, k, vh, vsky, vrin, vrout, atol, v0; };
+struct Consts64 { double s, k, vh, vsky, vrin, vrout, atol, v0; };
+
 inline BatchConst integ_consts(const DevScene& sc, const DevTol& t, double u0) {
     BatchConst c;
     const bool flat = !(sc.M > 0.0);

@@ -639,6 +639,19 @@ __device__ __forceinline__ void ray_consts(const BatchConst& c, T& s, T& k, T& v
     }
 }
 
+__device__ __forceinline__ void ray_consts(const Consts32& c, float& s, float& k, float& vh,
+                                           float& vsky, float& vrin, float& vrout, float& atol,
+                                           float& v0) {
+    s = c.s, k = c.k, vh = c.vh, vsky = c.vsky, vrin = c.vrin, vrout = c.vrout, atol = c.atol;
+    v0 = c.v0;
+}
+__device__ __forceinline__ void ray_consts(const Consts64& c, double& s, double& k, double& vh,
+                                           double& vsky, double& vrin, double& vrout,
+                                           double& atol, double& v0) {
+    s = c.s, k = c.k, vh = c.vh, vsky = c.vsky, vrin = c.vrin, vrout = c.vrout, atol = c.atol;
+    v0 = c.v0;
+}
+
 template <bool C, typename A, typename B> struct Pick { using type = A; };
 template <typename A, typename B> struct Pick<false, A, B> { using type = B; };
 
@@ -650,10 +663,11 @@ template <typename A, typename B> struct Pick<false, A, B> { using type = B; };
 // STATS: count accepted, rejected and Newton steps and capped rays into
 // the per-call statistics (an instrumented variant; the default one counts
 // nothing).
-template <typename T, bool VIRTUAL, bool BATCH, bool R32, bool KAPPA, bool STATS = false>
+template <typename T, bool VIRTUAL, bool BATCH, bool R32, bool KAPPA, bool STATS = false,
+          typename C = BatchConst>
 __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                           const double2* __restrict__ qrec, int64_t total, int32_t* heads,
-                          int nslices, T rtol, T ntol, const BatchConst* __restrict__ bct,
+                          int nslices, T rtol, T ntol, const C* __restrict__ bct,
                           int refill_min, int qblocks) {
     const int lane = lane_id();
     // constants in the scaled variable v = s u (s = 3M; s = 1, k = 0 for
@@ -909,33 +923,51 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     }
 }
 
-// Stages the integrator constants in LDS: a batch's per-request table, or a
-// single frame's constants.  The latter are read back from LDS, so the loop
-// holds them in vector registers; taken from the kernel arguments they would
-// sit in scalar registers, which the FP32 loop would then spill.
-template <bool BATCH>
-__device__ __forceinline__ const BatchConst* stage_consts(const IntegArgs& a) {
-    if constexpr (BATCH) {
-        extern __shared__ BatchConst s_bc[];
-        for (int k = threadIdx.x; k < a.nreq; k += blockDim.x) s_bc[k] = a.bconst[k];
-        __syncthreads();
-        return s_bc;
-    } else {
-        __shared__ BatchConst s_fc;
-        if (threadIdx.x == 0) s_fc = a.fc;
-        __syncthreads();
-        return &s_fc;
+// Stages the integrator constants in LDS: a single frame's constants, or a
+// batch's per-request table in one precision (C = Consts32 or Consts64; the
+// launch gives the kernel sizeof(C) bytes of LDS per request).  A single
+// frame's constants are read back from LDS, so the loop holds them in vector
+// registers; taken from the kernel arguments they would sit in scalar
+// registers, which the FP32 loop would then spill.
+__device__ __forceinline__ const BatchConst* stage_frame_consts(const IntegArgs& a) {
+    __shared__ BatchConst s_fc;
+    if (threadIdx.x == 0) s_fc = a.fc;
+    __syncthreads();
+    return &s_fc;
+}
+
+template <typename C>
+__device__ __forceinline__ const C* stage_batch_consts(const IntegArgs& a) {
+    extern __shared__ __align__(8) char s_tab[];
+    C* t = reinterpret_cast<C*>(s_tab);
+    for (int r = threadIdx.x; r < a.nreq; r += blockDim.x) {
+        const BatchConst& c = a.bconst[r];
+        if constexpr (sizeof(C) == sizeof(Consts32))
+            t[r] = C{c.s32, c.k32, c.vh32, c.vsky32, c.vrin32, c.vrout32, c.atol32, c.v032};
+        else
+            t[r] = C{c.s, c.k, c.vh, c.vsky, c.vrin, c.vrout, c.atol64, c.v0};
     }
+    __syncthreads();
+    return t;
 }
 
 // FP64 mode: one pass over all rays tagged FP64.  KAPPA: some ray's scene
 // is flat (M = 0), so g keeps its factor k.
 template <bool BATCH, bool KAPPA, bool STATS = false>
 __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
-    const BatchConst* bct = stage_consts<BATCH>(a);
-    run_queue<double, true, BATCH, false, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
-                                                 kSlices, a.tol.rtol64, a.tol.newton64, bct,
-                                                 a.tol.refill64, (int)gridDim.x);
+    if constexpr (BATCH) {
+        const Consts64* bct = stage_batch_consts<Consts64>(a);
+        run_queue<double, true, BATCH, false, KAPPA, STATS>(a, nullptr, nullptr, a.n,
+                                                     &a.w.ctr[kCtrMain], kSlices, a.tol.rtol64,
+                                                     a.tol.newton64, bct, a.tol.refill64,
+                                                     (int)gridDim.x);
+    } else {
+        const BatchConst* bct = stage_frame_consts(a);
+        run_queue<double, true, BATCH, false, KAPPA, STATS>(a, nullptr, nullptr, a.n,
+                                                     &a.w.ctr[kCtrMain], kSlices, a.tol.rtol64,
+                                                     a.tol.newton64, bct, a.tol.refill64,
+                                                     (int)gridDim.x);
+    }
 }
 
 // FP32 mode (batches keep FP32 records).  The first `band_blocks` blocks
@@ -946,20 +978,31 @@ __device__ __forceinline__ void integrate_fp64(const IntegArgs& a) {
 // ends inside the FP32 work instead of trailing it.
 template <bool BATCH, bool R32, bool KAPPA, bool STATS = false>
 __device__ __forceinline__ void integrate_fp32(const IntegArgs& a, int band_blocks) {
-    const BatchConst* bct = stage_consts<BATCH>(a);
+    // A batch stages its FP32 constants in LDS; its band rays, a fraction of
+    // a percent, read their FP64 constants from the global table at each
+    // start.  A single frame's constants sit in LDS for both.
+    const BatchConst* fc = nullptr;
+    const Consts32* t32 = nullptr;
+    if constexpr (BATCH) t32 = stage_batch_consts<Consts32>(a);
+    else fc = stage_frame_consts(a);
     if ((int)blockIdx.x < band_blocks) {
         __builtin_amdgcn_s_setprio(3);
         IntegArgs ab = a;
         ab.chunk = 64;
         run_queue<double, false, BATCH, R32, KAPPA, STATS>(ab, a.w.q64, a.w.q64rec,
                                                       a.w.ctr[kCtrBandSize], &a.w.ctr[kCtrBand], 1,
-                                                      a.tol.rtol64, a.tol.newton64, bct, 1,
-                                                      band_blocks);
+                                                      a.tol.rtol64, a.tol.newton64,
+                                                      BATCH ? a.bconst : fc, 1, band_blocks);
         __builtin_amdgcn_s_setprio(0);
     }
-    run_queue<float, true, BATCH, R32, KAPPA, STATS>(a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain],
-                                                kSlices, a.tol.rtol32, a.tol.newton32, bct,
-                                                a.tol.refill32, (int)gridDim.x);
+    if constexpr (BATCH)
+        run_queue<float, true, BATCH, R32, KAPPA, STATS, Consts32>(
+            a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices, a.tol.rtol32, a.tol.newton32,
+            t32, a.tol.refill32, (int)gridDim.x);
+    else
+        run_queue<float, true, BATCH, R32, KAPPA, STATS>(
+            a, nullptr, nullptr, a.n, &a.w.ctr[kCtrMain], kSlices, a.tol.rtol32, a.tol.newton32,
+            fc, a.tol.refill32, (int)gridDim.x);
 }
 
 template <bool KAPPA, bool STATS>
@@ -1569,7 +1612,9 @@ hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol
     a.bconst = b.bconst;
     a.nreq = b.nreq;
     a.fc = BatchConst{};  // unused: batch rays take their request's entry
-    const size_t lds_c = sizeof(BatchConst) * b.nreq;
+    // per-request constants staged in LDS: the FP32 ones for FP32 batches,
+    // the FP64 ones for FP64 batches
+    const size_t lds_c = (precision == 1 ? sizeof(Consts32) : sizeof(Consts64)) * b.nreq;
     if (b.any_flat) launch_batch_integrate_k<true>(a, b.total, lds_c, precision, cus, grid_blocks, s);
     else launch_batch_integrate_k<false>(a, b.total, lds_c, precision, cus, grid_blocks, s);
     return hipGetLastError();

@@ -156,6 +156,30 @@ def test_image_only_fp32_renders_equal_renders_with_outputs(bh):
                                           err_msg=f"{f.name} stats={stats}")
 
 
+def test_request_groups_must_fit_one_blocks_lds(bh):
+    """A group's integrator stages its requests' FP32 constants in LDS, 32
+    bytes each: 6000 one-pixel requests in one group (192 KB) are refused at
+    creation, and in two groups (96 KB each) they render as single renders."""
+    import torch
+    rng = np.random.default_rng(5)
+    frames = []
+    for k in range(6000):
+        cam = inputs.Camera(float(rng.uniform(15.0, 90.0)), float(rng.uniform(0, 90)),
+                            float(rng.uniform(0, 360)), 40.0, 1, 1)
+        frames.append(inputs.Frame(cam, inputs.scene_in_m(1.0, (6.0, 20.0) if k % 2 else None), f"p{k}"))
+    with pytest.raises(bh.BhError) as err:
+        bh.Batch(frames, bh.options(precision=bh.FP32, batch_groups=1), use_graph=False)
+    assert err.value.status == bh.BH_ERR_ARG and "batch_groups" in str(err.value)
+    b = bh.Batch(frames, bh.options(precision=bh.FP32, batch_groups=2), use_graph=False)
+    b.launch()
+    torch.cuda.synchronize()
+    assert b.stats()["requests"] == 6000
+    for k in range(0, 6000, 997):
+        want = _single(bh, [frames[k]], bh.FP32)[0]
+        np.testing.assert_array_equal(b.images[k].cpu().numpy(), want, err_msg=f"request {k}")
+    b.close()
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_groups(bh, graph):
     """Requests split into up to 3 consecutive groups traced one after another:
