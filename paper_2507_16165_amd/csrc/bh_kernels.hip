@@ -655,11 +655,13 @@ __device__ __forceinline__ void ray_consts(const Consts64& c, double& s, double&
 template <bool C, typename A, typename B> struct Pick { using type = A; };
 template <typename A, typename B> struct Pick<false, A, B> { using type = B; };
 
-// Constants come from a table staged in LDS (`bct`): one entry for a single
-// frame; with BATCH, rays of several requests share the queue and each ray's
-// request index selects its entry.
-// R32 (FP32 batches): main-queue start records come from a.w.rec32 and result
-// records go to a.w.res32.
+// Constants come from a table (`bct`, of type C): one entry in LDS for a
+// single frame; with BATCH, rays of several requests share the queue and each
+// ray's request index selects its entry (a per-request table in LDS in the
+// queue's precision, or the global BatchConst table for the band rays of an
+// FP32 batch).
+// R32 (FP32 batches and image-only FP32 renders): main-queue start records
+// come from a.w.rec32 and result records go to a.w.res32.
 // STATS: count accepted, rejected and Newton steps and capped rays into
 // the per-call statistics (an instrumented variant; the default one counts
 // nothing).
