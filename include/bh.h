@@ -113,7 +113,8 @@ typedef struct {
     int    grid_blocks;      /* persistent integrator grid, 256-thread blocks; 0 = auto
                                 (single renders and traces: 3/4 of the resident
                                 blocks; batches: all resident blocks)               */
-    int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto  */
+    int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto
+                                (512 for FP32 batches, 256 otherwise)                */
     int    samples_side;     /* bh_render: n x n rays per pixel at the stratified
                                 sub-pixel centres, averaged (box filter); 0 or 1 =
                                 one ray through the pixel centre; at most 16        */
@@ -130,7 +131,7 @@ typedef struct {
                                 trained network (NULL = off; see bh_surrogate_*)     */
     int    refill_fp32;      /* persistent integrator: a wavefront starts new FP32 rays
                                 once this many of its 64 lanes are idle (or its queue is
-                                dry); 1..64, 0 = auto (20).  Any value gives the same
+                                dry); 1..64, 0 = auto (28).  Any value gives the same
                                 results; it only changes the schedule                 */
     int    refill_fp64;      /* the same for the FP64 rays of FP64 mode; 0 = auto (6).
                                 (The critical band of FP32 mode always refills at 1.) */

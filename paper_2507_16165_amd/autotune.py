@@ -23,7 +23,7 @@ from . import api
 
 BLOCKS_PER_CU = (4, 6, 8)
 CHUNKS = (128, 256, 512, 1024)
-REFILLS_FP32 = (1, 8, 14, 20, 28)
+REFILLS_FP32 = (1, 8, 14, 20, 28, 36)
 REFILLS_FP64 = (1, 3, 6, 10)
 GROUPS = (1, 2, 4, 8)
 KNOBS = ("grid_blocks", "chunk", "refill", "batch_groups")
@@ -86,7 +86,8 @@ def tune_batch(frames, precision: int, workload: str, cache_path: str | None = N
         "refill": list(REFILLS_FP32 if precision == api.FP32 else REFILLS_FP64),
         "batch_groups": [g for g in GROUPS if g <= len(frames)],
     }
-    best = {"grid_blocks": cus * 8, "chunk": 256, "refill": 20 if precision == api.FP32 else 6,
+    best = {"grid_blocks": cus * 8, "chunk": 512 if precision == api.FP32 else 256,
+            "refill": 28 if precision == api.FP32 else 6,
             "batch_groups": 0}
     best["ms"] = time_batch(frames, _options(precision, best), images, reps)
     seen = {tuple(best[k] for k in KNOBS): best["ms"]}

@@ -607,7 +607,7 @@ __device__ __forceinline__ double recip(double x) {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Idle lanes a wavefront waits for before it starts new rays come from the
-// options (DevTol::refill32 / refill64; defaults 20 and 6).  The FP64
+// options (DevTol::refill32 / refill64; defaults 28 and 6).  The FP64
 // critical band of FP32 mode, whose rays are long, refills at once.
 
 // Drains one queue.  VIRTUAL: the queue is the index range [0, total) and
