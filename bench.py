@@ -50,10 +50,10 @@ PEAK_FP64_TFLOPS = 78.6
 SCALAR_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_integrate_fp32_batch_orbit4k_traffic.txt")
 ROOFLINE_KERNEL = "bh::k_integrate_fp32_batch<false>"
-# HBM bytes per ray of the batch integrator (FP32 batches keep FP32 records):
-# start record (8 B) and request index (4 B) read, result record (8 B) and
-# class/step word (4 B) written
-BYTES_PER_RAY = 24
+# HBM bytes per ray of the batch integrator (FP32 batches keep FP32 records,
+# whose result record carries the end class): start record (8 B) and request
+# index (4 B) read, result record (8 B) written
+BYTES_PER_RAY = 20
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2507_16165_amd", "csrc", f)
                for f in ("bh_kernels.hip", "bh_internal.h")]
 

@@ -20,6 +20,16 @@ constexpr int kWave = 64;     // CDNA wavefront
 enum : uint8_t { SKY = 0, CAPTURED = 1, DISK = 2, UNRESOLVED = 3, INVALID = 4 };
 enum : uint8_t { PATH_NONE = 0, PATH_FP64 = 1, PATH_FP32 = 2, PATH_SUR = 3 };
 
+// FP32 result records (Work::res32) hold the end class in their r_hit field:
+// a disk hit's radius (> 0), or minus the class for every other end (SKY 0,
+// CAPTURED -1, UNRESOLVED -3, INVALID -4; small integers, exact in float).
+__device__ __forceinline__ float rec32_radius(uint8_t cls, float r_hit) {
+    return cls == DISK ? r_hit : (float)(-(int)cls);
+}
+__device__ __forceinline__ uint8_t rec32_class(float r) {
+    return r > 0.0f ? (uint8_t)DISK : (uint8_t)(int)(-r);
+}
+
 // Surrogate trust map: 256 bins of ln(b - b_c) x 64 bins of r0 (see trust_bin).
 constexpr int kTrustB = 256, kTrustR = 64;
 
@@ -110,12 +120,15 @@ struct Work {
     float2* rec32;
     double2* res;             // result record {phi_end, r_hit}
     // set together with rec32: the result record as {phi_end, r_hit} in FP32,
-    // the FP32 shading's inputs, in res's memory; NULL otherwise
+    // the FP32 shading's inputs, in res's memory; NULL otherwise.  Its r_hit
+    // also carries the end class (rec32_radius), so that shading reads
+    // nothing else: clst is then written only by statistics runs and by the
+    // rays that end at set-up or in the surrogate.
     float2* res32;
     int32_t* qsur;            // surrogate list (kSurSlices slices): ray indices ...
     double2* qsurrec;         // ... and {b, w0}
     int32_t* rq;              // batch: request index of each ray
-    int32_t* clst;            // class | (step evaluations << 3)
+    int32_t* clst;            // class | (step evaluations << 3) (see res32)
     uint8_t* path;
     int32_t* q64;             // FP64 band queue (FP32 mode): ray indices ...
     double2* q64rec;          // ... and their start records

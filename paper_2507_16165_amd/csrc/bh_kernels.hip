@@ -248,7 +248,7 @@ __device__ __forceinline__ int setup_ray(const Basis& B, const DevScene& sc, con
     if (R32) w.rec32[i] = make_float2(main ? (float)w0 : __builtin_nanf(""), (float)phi1);
     else w.rec[i] = make_double2(main ? w0 : nan_d(), phi1);
     if (path == PATH_NONE) {
-        if (R32) w.res32[i] = make_float2((float)phi_end, 0.0f);
+        if (R32) w.res32[i] = make_float2((float)phi_end, rec32_radius(cls, 0.0f));
         else w.res[i] = make_double2(phi_end, 0.0);
         w.clst[i] = cls;
     }
@@ -299,7 +299,7 @@ __device__ __forceinline__ int setup_camera32(const DevCam& cam, const DevScene&
         if (!BATCH) w.path[g] = PATH_NONE;
         if (R32) {
             w.rec32[g] = make_float2(__builtin_nanf(""), 0.0f);
-            w.res32[g] = make_float2(0.0f, 0.0f);
+            w.res32[g] = make_float2(0.0f, rec32_radius(CAPTURED, 0.0f));
         } else {
             w.rec[g] = make_double2(nan_d(), 0.0);
             w.res[g] = make_double2(0.0, 0.0);
@@ -913,13 +913,17 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
             // below their integration error; an IEEE division here cost
             // about ten instructions in the block every finishing ray runs)
             const double rh = !disk_hit ? 0.0 : (double)(s * recip(vn));
-            if (R32) a.w.res32[id] = make_float2((float)pe, (float)rh);
+            if (R32) a.w.res32[id] = make_float2((float)pe, rec32_radius(cls, (float)rh));
             else a.w.res[id] = make_double2(pe, rh);
             // Step evaluations: the trial steps, plus the Newton re-steps of a
             // sky crossing (a ray in refinement ends only there; its last
             // update is the it_new-th, the first came from the trial step).
-            const int nsteps = attempts + (sky_done ? it_new - 1 : 0);
-            a.w.clst[id] = (int32_t)cls | (nsteps << 3);
+            // FP32 records carry the class, and only statistics runs read the
+            // counts then.
+            if (!R32 || STATS) {
+                const int nsteps = attempts + (sky_done ? it_new - 1 : 0);
+                a.w.clst[id] = (int32_t)cls | (nsteps << 3);
+            }
             active = false;
         }
     }
@@ -1260,15 +1264,16 @@ __device__ __forceinline__ float4 shade_px32(const Basis32& B, const DevScene& s
     return px;
 }
 
-// R32: the record is read from w.res32 (FP32 batches).
+// R32: the record, class included, is read from w.res32 (FP32 batches and
+// image-only FP32 renders, which return no per-ray outputs).
 template <bool R32 = false>
 __device__ __forceinline__ void shade_ray32(const Basis32& B, const DevScene& sc, const Work& w,
                                             int64_t i, float4* px_out, const Out& out,
                                             int64_t oi) {
-    const int32_t cs = w.clst[i];
-    const uint8_t cls = (uint8_t)(cs & 7);
+    const int32_t cs = R32 ? 0 : w.clst[i];
     const double2 rr = R32 ? make_double2(0.0, 0.0) : w.res[i];
     const float2 rf = R32 ? w.res32[i] : make_float2((float)rr.x, (float)rr.y);
+    const uint8_t cls = R32 ? rec32_class(rf.y) : (uint8_t)(cs & 7);
     float sv[3];
     const float4 px = shade_px32(B, sc, cls, rf.x, rf.y, sv);
     if (px_out) *px_out = px;
@@ -1343,6 +1348,10 @@ __global__ __launch_bounds__(kBlock) void k_shade(Source src, DevScene sc, Work 
 // finish time (one atomic per chunk and request, so the counters of large
 // requests are not contended).
 constexpr int kShadeChunk = 32 * kBlock;
+// Blocks per CU of batch shading.  On the 16 4K orbit frames (FP32: 8 B of
+// records read and 16 B of image written per ray) 6 shaded in 0.69-0.71 ms,
+// 4 in 0.83, 5 in 0.76 and 7 (the occupancy limit at 71 VGPRs) in 0.82.
+constexpr int kShadeBlocksPerCu = 6;
 
 template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_shade_batch(BatchDev b, Work w) {
@@ -1632,12 +1641,14 @@ hipError_t launch_batch_shade(const BatchDev& b, const Work& w, int precision, i
     if (b.total == 0) return hipSuccess;
     if (precision == 1 && !w.res32) return hipErrorInvalidValue;  // FP32 batches: FP32 records
     const size_t lds_off = sizeof(int64_t) * (b.nreq + 1);
-    // One round of resident blocks: a grid beyond them would leave a second,
-    // partly filled round of blocks at the end.
+    // One round of resident blocks, at most kShadeBlocksPerCu per CU: a grid
+    // beyond them would leave a second, partly filled round of blocks at the
+    // end.
     const int per_cu = precision == 1 ? blocks_per_cu_lds(k_shade_batch<true>, lds_off)
                                       : blocks_per_cu_lds(k_shade_batch<false>, lds_off);
+    const int64_t slots = (int64_t)cus * min(per_cu, kShadeBlocksPerCu);
     int64_t gs = (b.total + kShadeChunk - 1) / kShadeChunk;
-    if (gs > (int64_t)cus * per_cu) gs = (int64_t)cus * per_cu;
+    if (gs > slots) gs = slots;
     if (precision == 1) k_shade_batch<true><<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
     else k_shade_batch<false><<<(unsigned)gs, kBlock, lds_off, s>>>(b, w);
     return hipGetLastError();

@@ -597,9 +597,13 @@ __device__ inline void sur_finish(const SurRender& a, int id, double w0, float b
     }
     const float ib = __builtin_amdgcn_rcpf(bm);
     const float phi = sweep1f(bm, ib, inv_r0m) + (12.0f * ib * ib) * y0;
-    if constexpr (BATCH) a.w.res32[id] = make_float2(phi, 0.0f);
-    else a.w.res[id] = make_double2((double)phi, 0.0);
-    a.w.clst[id] = 0;  // SKY, no integration steps
+    // SKY, no integration steps (an FP32 record's zero r_hit is the class)
+    if constexpr (BATCH) {
+        a.w.res32[id] = make_float2(phi, 0.0f);
+    } else {
+        a.w.res[id] = make_double2((double)phi, 0.0);
+        a.w.clst[id] = 0;
+    }
 }
 
 // Entry of listed ray j of tile t: tiles are numbered over the slices in

@@ -139,21 +139,38 @@ def test_batch_edge_requests_equal_single_renders(bh, precision, graph):
 
 def test_image_only_fp32_renders_equal_renders_with_outputs(bh):
     """An FP32 render that returns only the image keeps FP32 start and result
-    records (as FP32 batches do); one that also returns per-pixel outputs keeps
-    FP64 records.  The pixels must be the same bit for bit: ragged and 1x1
-    frames, disks, sky images, flat space, distant and close cameras, with and
-    without the per-call statistics (the instrumented integrator)."""
+    records (as FP32 batches do), whose r_hit also carries the end class; one
+    that also returns per-pixel outputs keeps FP64 records and the class word.
+    The pixels must be the same bit for bit: ragged and 1x1 frames, disks, sky
+    images, flat space, distant and close cameras, with and without the
+    per-call statistics (the instrumented integrator), and with a step cap of
+    6 that leaves many rays unresolved (black, where a misread class would
+    give sky or disk), in single renders and in an FP32 batch."""
     import torch
     frames = mixed_frames() + edge_frames()
-    for stats in (0, 1):
-        opt = bh.options(precision=bh.FP32, collect_stats=stats)
+    capped = bh.options(precision=bh.FP32, max_steps=6)
+    n_unresolved = 0
+    refs = []
+    for opt, tag in ((bh.options(precision=bh.FP32), "plain"),
+                     (bh.options(precision=bh.FP32, collect_stats=1), "stats"),
+                     (capped, "capped")):
         for f in frames:
             img, _ = bh.render(f.camera, f.scene, opt)
             ref, out = bh.render(f.camera, f.scene, opt, fields=("cls",))
             torch.cuda.synchronize()
             assert out is not None and "cls" in out
             np.testing.assert_array_equal(img.cpu().numpy(), ref.cpu().numpy(),
-                                          err_msg=f"{f.name} stats={stats}")
+                                          err_msg=f"{f.name} {tag}")
+            if tag == "capped":
+                n_unresolved += int((out["cls"] == bh.UNRESOLVED).sum().item())
+                refs.append(ref.cpu().numpy())
+    assert n_unresolved > 1000, n_unresolved
+    b = bh.Batch(frames, capped, use_graph=False)
+    b.launch()
+    torch.cuda.synchronize()
+    for f, img, ref in zip(frames, b.images, refs):
+        np.testing.assert_array_equal(img.cpu().numpy(), ref, err_msg=f"{f.name} batch capped")
+    b.close()
 
 
 def test_request_groups_must_fit_one_blocks_lds(bh):
