@@ -931,7 +931,6 @@ bh_status bh_batch_create(const bh_request* reqs, int n, const bh_options* opt, 
     d.bconst = d_bc;
     d.done = d_done;
     d.stamp = d_stamp;
-    d.req_host0 = req[0].sc;
     d.any_flat = any_flat;
     d.any_sur = any_sur;
     if (any_sur) {

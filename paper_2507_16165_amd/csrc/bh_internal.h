@@ -251,7 +251,6 @@ struct BatchDev {
     const BatchConst* bconst;
     unsigned long long* done;      // pixels shaded per request
     unsigned long long* stamp;     // finish clock per request; stamp[nreq] = start
-    DevScene req_host0;            // unused placeholder scene for the integrator args
     int any_flat;                  // some request has M = 0 (integrator variant with k)
     int any_sur;                   // some request routes rays to the surrogate
 };

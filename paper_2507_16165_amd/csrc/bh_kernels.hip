@@ -1621,7 +1621,7 @@ hipError_t launch_batch_integrate(const BatchDev& b, const Work& w, const DevTol
     a.n = b.total;
     a.u0 = nullptr;
     a.u0_uniform = 0.0;
-    a.sc = b.req_host0;  // placeholders; the batch kernels read per-request constants
+    a.sc = DevScene{};  // read by the fixed-step kernel only; batch rays use their request's
     a.tol = tol;
     a.w = w;
     a.chunk = chunk;
