@@ -138,6 +138,12 @@ typedef struct {
     int    collect_stats;    /* bh_render / bh_trace_rays: 1 = count the statistics that
                                 bh_last_stats reports, with an instrumented integrator (the
                                 same results, somewhat slower); 0 = off.  Batches: must be 0 */
+    double rtol_fp32_growth; /* FP32 rays: their tolerance grows with the distance of the
+                                impact parameter from the critical value, where the exit
+                                direction is less sensitive to integration error: rtol =
+                                rtol_fp32 * clamp(|b - 3 sqrt(3) M| / (0.5 M), 1, growth),
+                                atol likewise, first step h0_fp32 * (that factor)^(1/5).
+                                1 = the same tolerance for every ray; in [1, 1e4]      */
 } bh_options;
 
 /* Optional per-ray outputs (device arrays of length n, any may be NULL).
@@ -154,9 +160,9 @@ typedef struct {
 } bh_ray_out;
 
 /* Fills defaults: FP64, rtol 1e-10, atol 0 (-> rtol/r_sky), rtol_fp32 1e-6,
- * band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps 1e6, analytic capture
- * on, auto launch shape, refill thresholds and batch groups.  Returns BH_ERR_ARG
- * for NULL. */
+ * rtol_fp32_growth 20, band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps
+ * 1e6, analytic capture on, auto launch shape, refill thresholds and batch groups.
+ * Returns BH_ERR_ARG for NULL. */
 bh_status bh_default_options(bh_options* opt);
 
 /* Traces n rays with world-space origins and directions (device, n*3 doubles

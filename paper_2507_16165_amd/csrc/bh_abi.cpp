@@ -199,6 +199,8 @@ bh_status check_opt(const bh_options* o) {
     if (!finite_pos(o->rtol) || !finite_pos(o->rtol_fp32))
         return fail(BH_ERR_ARG, "tolerances must be > 0");
     if (!isfinite(o->atol)) return fail(BH_ERR_ARG, "atol must be finite");
+    if (!(o->rtol_fp32_growth >= 1.0 && o->rtol_fp32_growth <= 1e4))
+        return fail(BH_ERR_ARG, "rtol_fp32_growth must lie in [1, 1e4]");
     if (!(isfinite(o->band_halfwidth) && o->band_halfwidth >= 0.0))
         return fail(BH_ERR_ARG, "band_halfwidth must be >= 0");
     if (!finite_pos(o->h0) || !finite_pos(o->h0_fp32) || !finite_pos(o->hmax) ||
@@ -248,6 +250,7 @@ bh::DevTol dev_tol(const bh_options* o, const bh_scene* sc) {
     t.atol64 = o->atol > 0.0 ? o->atol : o->rtol / sc->r_sky;
     t.rtol32 = (float)o->rtol_fp32;
     t.atol32 = (float)(o->rtol_fp32 / sc->r_sky);
+    t.grow32 = (float)o->rtol_fp32_growth;
     t.h0 = o->h0;
     t.h0_32 = o->h0_fp32;
     t.hmax = o->hmax;
@@ -549,6 +552,11 @@ bh_status bh_default_options(bh_options* o) {
     o->rtol = 1e-10;
     o->atol = 0.0;
     o->rtol_fp32 = 1e-6;
+    // FP32 rays far from the critical curve take up to 20x the tolerance.  On
+    // the 16 4K orbit frames that leaves the largest exit and disk-radius
+    // errors where they were (rays next to the critical band, which keep the
+    // base tolerance) and takes 7.5 instead of 11.2 step evaluations per ray.
+    o->rtol_fp32_growth = 20.0;
     o->band_halfwidth = 0.05;
     o->h0 = 1e-2;
     // The FP32 path starts near the step its tolerance allows in the far

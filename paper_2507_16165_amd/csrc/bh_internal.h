@@ -73,6 +73,7 @@ struct DevScene {
 struct DevTol {
     double rtol64, atol64;
     float rtol32, atol32;
+    float grow32;             // largest factor on an FP32 ray's rtol32 and atol32 (>= 1)
     double h0, h0_32, hmax, max_phi;  // h0_32: first step of the FP32 integrator
     double newton64;          // Newton stop on |dh| for the sky crossing
     float newton32;

@@ -652,6 +652,21 @@ __device__ __forceinline__ void ray_consts(const Consts64& c, double& s, double&
     v0 = c.v0;
 }
 
+// Tolerance factor of an FP32 ray, in [1, grow]: |b - 3 sqrt(3) M| / (0.5 M),
+// clamped.  Near the critical impact parameter the sweep's sensitivity to
+// integration error grows like 1/|b - b_c|, so a tolerance proportional to
+// that distance keeps the exit error about even across rays; the rays next to
+// the critical band keep the base tolerance.  b/M from the ray's start: with
+// v = 3M u and w = dv/dphi, 9 M^2 / b^2 = w^2 + v^2 - (2/3) v^3 (the first
+// integral of Eq. (1)); k = 0 drops the cubic for flat space, where any
+// factor in [1, grow] is as good.  The start has v < 1 (outside the photon
+// sphere), so the sum is positive.
+__device__ __forceinline__ float tol_growth(float v, float w, float k, float grow) {
+    const float e = fmaf(w, w, v * v * fmaf(-0.666666667f * k, v, 1.0f));
+    const float bm = 3.0f * __builtin_amdgcn_rsqf(e);
+    return __builtin_amdgcn_fmed3f(fabsf(bm - 5.19615242f) * 2.0f, 1.0f, grow);
+}
+
 template <bool C, typename A, typename B> struct Pick { using type = A; };
 template <typename A, typename B> struct Pick<false, A, B> { using type = B; };
 
@@ -680,6 +695,9 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
     const T max_phi = T(a.tol.max_phi);
     const int max_steps = a.tol.max_steps;
     int pf_rq = 0;
+    // the ray's relative tolerance (FP32 rays: rtol times tol_growth, set at
+    // the ray's start, atol scaled alike)
+    T rt = rtol;
 
     // ray state
     T v = T(0), w = T(0), g = T(0), h = T(0), hh = T(0);
@@ -731,6 +749,15 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
                 w = s * T(pf.x);
                 g = g_scaled<KAPPA>(k, v);
                 h = h0;
+                if constexpr (sizeof(T) == 4) {
+                    // the first step grows with the tolerance as the
+                    // controller's steps do (local error ~ h^5)
+                    const float f = tol_growth(v, w, k, a.tol.grow32);
+                    if constexpr (!BATCH) atol = bct[0].atol32;
+                    rt = rtol * f;
+                    atol *= f;
+                    if (f > 1.0f) h = h0 * __builtin_amdgcn_exp2f(0.2f * __builtin_amdgcn_logf(f));
+                }
                 phi = T(0);
                 phik = T(pf.y);
                 attempts = 0;
@@ -836,8 +863,8 @@ __device__ void run_queue(const IntegArgs& a, const int32_t* __restrict__ queue,
         // Error test: accept iff |e_i| <= atol + rtol max(|y_i|, |y_new_i|)
         // for both components (exact comparison); the ratio for the step-size
         // proposal needs one reciprocal.
-        const T su = fma(rtol, max_abs(v, vn), atol);
-        const T sw = fma(rtol, max_abs(w, wn), atol);
+        const T su = fma(rt, max_abs(v, vn), atol);
+        const T sw = fma(rt, max_abs(w, wn), atol);
         const bool fits = (fabs(eu) <= su) & (fabs(ew) <= sw);
         const float fsu = (float)su, fsw = (float)sw;
         // |e| fs = |e fs| (fs > 0, rounding is sign-symmetric): the absolute

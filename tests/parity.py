@@ -21,8 +21,9 @@ answers are correct to the method's accuracy:
   - the critical band |b - 3 sqrt(3) M| < 0.05 M (ill-conditioned sweep),
   - disk edges: a DISK/non-DISK disagreement is allowed only if the DISK
     side's hit radius lies within tau_r of r_in or r_out,
-  - checker cell boundaries (colour only): oracle theta or varphi within
-    tau_theta of a multiple of the cell size.
+  - checker cell boundaries (colour only): oracle theta within tau_theta,
+    or varphi within tau_theta / sin(theta), of a multiple of the cell size
+    (a direction error of tau_theta moves the azimuth by up to that much).
 
 Band rays.  Inside the band the FP64 integrator still serves the rays (in
 FP32 mode too), and rays of equal class are compared with a bound from the
@@ -84,16 +85,20 @@ def radius_per_azimuth(b, r, M):
 
 
 def near_cell_boundary(s, cell_deg, tau):
+    """Exit directions within tau radians of a checker boundary: a direction
+    error of tau moves theta by up to tau and the azimuth varphi by up to
+    tau / sin(theta), so the azimuth zone widens toward the poles."""
     s = np.asarray(s, float).reshape(-1, 3)
     theta = np.arctan2(np.hypot(s[:, 0], s[:, 1]), s[:, 2])
     varphi = np.mod(np.arctan2(s[:, 1], s[:, 0]), 2 * np.pi)
     cell = math.radians(cell_deg)
+    tau_phi = tau / np.maximum(np.sin(theta), 1e-300)
 
-    def near(x):
+    def near(x, t):
         f = x / cell
-        return np.abs(f - np.round(f)) * cell < tau
+        return np.abs(f - np.round(f)) * cell < t
 
-    return near(theta) | near(varphi) | (varphi < tau) | (2 * np.pi - varphi < tau)
+    return near(theta, tau) | near(varphi, tau_phi) | (varphi < tau_phi) | (2 * np.pi - varphi < tau_phi)
 
 
 def _zones(ref_rays, scene, band):

@@ -97,6 +97,28 @@ def test_disk_frame_fp32_band(bh, ref, size):
     assert s["max_angle"] <= 1e-4
 
 
+@pytest.mark.parametrize("growth", [1.0, 20.0, 100.0])
+def test_fp32_tolerance_growth(bh, ref, growth):
+    """FP32 rays' tolerance grows with |b - b_c| up to `growth` times the
+    base (20 by default).  Every setting is held to the oracle at the FP32
+    bounds on a 400x400 disk frame (every 8th row), growth 100 as a stress of
+    the schedule; the grown tolerance takes fewer step evaluations per FP32
+    ray."""
+    f = inputs.disk_1024(400)
+    rgba, out = gpu_render(bh, f, bh.FP32, rtol_fp32_growth=growth)
+    rows = list(range(0, f.camera.height, 8))
+    r_rgba, r_rays, mask = oracle_rows(ref, f, rows)
+    s = compare(r_rays, out, f.scene, "fp32", mask=mask)
+    compare_rgba(r_rgba, r_rays, rgba, out["cls"], f.scene, "fp32", mask=mask)
+    fp32 = out["path"] == bh.PATH_FP32
+    steps = float(out["steps"][fp32].mean())
+    base = gpu_render(bh, f, bh.FP32, rtol_fp32_growth=1.0)[1]["steps"][fp32].mean()
+    print(f"growth {growth}: {steps:.2f} step evaluations per FP32 ray (growth 1: {base:.2f}), "
+          f"max exit angle {s['max_angle']:.3g} rad")
+    if growth > 1.0:
+        assert steps < 0.85 * base
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("disk", [None, (6.0, 20.0)])
 def test_band_rays_match_oracle(bh, ref, precision, disk):
