@@ -299,7 +299,7 @@ def main() -> int:
                         "checker sky, FP32 integrator + FP64 band |b-3sqrt3 M|<0.05M",
             "frames": len(frames), "width": W, "height": H, "rays_per_step": rays_per_step,
             "rtol_fp32": opt_fast.rtol_fp32, "rtol_fp32_growth": opt_fast.rtol_fp32_growth,
-            "rtol_fp64": opt_fast.rtol,
+            "rtol_band": opt_fast.rtol_band, "rtol_fp64": opt_fast.rtol,
         },
         "per_frame_renders": {"value": round(value_frames, 2), "unit": "Mrays/s",
                               "ms_per_step": round(ms_frames, 4),
@@ -421,14 +421,15 @@ def accuracy_leg(frames, api, torch, opt32):
             pairs[f"{int(b['cls'][i])}->{int(a['cls'][i])}"] = pairs.get(
                 f"{int(b['cls'][i])}->{int(a['cls'][i])}", 0) + 1
         band += int(in_band.sum().item())
-        # band rays 1e-3 M <= |b - b_c| < 0.05 M: both sides FP64-integrated;
-        # end azimuths within 1e-8 + b 1e-10 / |b - b_c| (the parity tests' band bound)
+        # band rays 1e-3 M <= |b - b_c| < 0.05 M: both sides FP64-integrated (FP32 mode's
+        # band at rtol_band, the FP64 kernel at 1e-10); end azimuths within
+        # 1e-8 + b (rtol_band + 1e-10) / |b - b_c| (the parity tests' band bound)
         dist = (b["b"] - bc).abs()
         shallow = in_band & (dist >= 1e-3 * M)
         bsame = shallow & same & ((b["cls"] == 0) | (b["cls"] == 2))
         band_mism += int((shallow & ~same & ~edge_zone).sum().item())
         if bool(bsame.any()):
-            lim = 1e-8 + b["b"][bsame] * 1e-10 / dist[bsame]
+            lim = 1e-8 + b["b"][bsame] * (opt32.rtol_band + 1e-10) / dist[bsame]
             band_worst = max(band_worst, float(((a["phi_end"][bsame] - b["phi_end"][bsame]).abs()
                                                 / lim).max().item()))
             band_n += int(bsame.sum().item())

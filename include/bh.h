@@ -98,8 +98,8 @@ typedef struct {
 
 typedef struct {
     int    precision;        /* BH_FP64, or BH_FP32 with FP64 kept for the critical band */
-    double rtol;             /* FP64 integrator relative tolerance                      */
-    double atol;             /* FP64 absolute tolerance; <= 0 means rtol / r_sky        */
+    double rtol;             /* FP64 mode: the integrator's relative tolerance          */
+    double atol;             /* FP64 mode: absolute tolerance; <= 0 means rtol / r_sky  */
     double rtol_fp32;        /* FP32 integrator tolerance; atol = rtol_fp32 / r_sky     */
     double band_halfwidth;   /* FP32 mode: |b - 3 sqrt(3) M| < band_halfwidth * M -> FP64 */
     double h0;               /* first trial step in phi (FP64 integrator)               */
@@ -144,6 +144,10 @@ typedef struct {
                                 rtol_fp32 * clamp(|b - 3 sqrt(3) M| / (0.5 M), 1, growth),
                                 atol likewise, first step h0_fp32 * (that factor)^(1/5).
                                 1 = the same tolerance for every ray; in [1, 1e4]      */
+    double rtol_band;        /* FP32 mode: relative tolerance of the FP64 integrator that
+                                serves the critical band (atol = rtol_band / r_sky).  A
+                                band ray's exit error is about b rtol_band / |b - b_c|,
+                                5.2e-6 rad at |b - b_c| = 1e-3 M for 1e-9               */
 } bh_options;
 
 /* Optional per-ray outputs (device arrays of length n, any may be NULL).
@@ -160,7 +164,7 @@ typedef struct {
 } bh_ray_out;
 
 /* Fills defaults: FP64, rtol 1e-10, atol 0 (-> rtol/r_sky), rtol_fp32 1e-6,
- * rtol_fp32_growth 20, band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps
+ * rtol_fp32_growth 20, rtol_band 1e-9, band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps
  * 1e6, analytic capture on, auto launch shape, refill thresholds and batch groups.
  * Returns BH_ERR_ARG for NULL. */
 bh_status bh_default_options(bh_options* opt);

@@ -44,7 +44,8 @@ class Options(C.Structure):
                 ("analytic_capture", C.c_int), ("grid_blocks", C.c_int), ("chunk", C.c_int),
                 ("samples_side", C.c_int), ("batch_groups", C.c_int), ("fixed_eps", C.c_double),
                 ("surrogate", C.c_void_p), ("refill_fp32", C.c_int), ("refill_fp64", C.c_int),
-                ("collect_stats", C.c_int), ("rtol_fp32_growth", C.c_double)]
+                ("collect_stats", C.c_int), ("rtol_fp32_growth", C.c_double),
+                ("rtol_band", C.c_double)]
 
 
 class Stats(C.Structure):

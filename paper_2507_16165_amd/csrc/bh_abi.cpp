@@ -199,6 +199,7 @@ bh_status check_opt(const bh_options* o) {
     if (!finite_pos(o->rtol) || !finite_pos(o->rtol_fp32))
         return fail(BH_ERR_ARG, "tolerances must be > 0");
     if (!isfinite(o->atol)) return fail(BH_ERR_ARG, "atol must be finite");
+    if (!finite_pos(o->rtol_band)) return fail(BH_ERR_ARG, "rtol_band must be > 0");
     if (!(o->rtol_fp32_growth >= 1.0 && o->rtol_fp32_growth <= 1e4))
         return fail(BH_ERR_ARG, "rtol_fp32_growth must lie in [1, 1e4]");
     if (!(isfinite(o->band_halfwidth) && o->band_halfwidth >= 0.0))
@@ -246,8 +247,14 @@ bh::DevScene dev_scene(const bh_scene* sc) {
 
 bh::DevTol dev_tol(const bh_options* o, const bh_scene* sc) {
     bh::DevTol t;
-    t.rtol64 = o->rtol;
-    t.atol64 = o->atol > 0.0 ? o->atol : o->rtol / sc->r_sky;
+    // FP32 mode integrates only its critical band in FP64, at rtol_band
+    if (o->precision == BH_FP32) {
+        t.rtol64 = o->rtol_band;
+        t.atol64 = o->rtol_band / sc->r_sky;
+    } else {
+        t.rtol64 = o->rtol;
+        t.atol64 = o->atol > 0.0 ? o->atol : o->rtol / sc->r_sky;
+    }
     t.rtol32 = (float)o->rtol_fp32;
     t.atol32 = (float)(o->rtol_fp32 / sc->r_sky);
     t.grow32 = (float)o->rtol_fp32_growth;
@@ -557,6 +564,12 @@ bh_status bh_default_options(bh_options* o) {
     // errors where they were (rays next to the critical band, which keep the
     // base tolerance) and takes 7.5 instead of 11.2 step evaluations per ray.
     o->rtol_fp32_growth = 20.0;
+    // The critical band of FP32 mode needs the FP32 path's 1e-4 rad, not the
+    // FP64 mode's accuracy: at 1e-9 a band ray's exit error, b rtol / |b - b_c|,
+    // stays below 5.2e-6 rad wherever band rays are compared (|b - b_c| >=
+    // 1e-3 M), and one-frame renders end sooner (their longest band rays set
+    // the end of the launch).
+    o->rtol_band = 1e-9;
     o->band_halfwidth = 0.05;
     o->h0 = 1e-2;
     // The FP32 path starts near the step its tolerance allows in the far

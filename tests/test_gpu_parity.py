@@ -127,9 +127,10 @@ def test_band_rays_match_oracle(bh, ref, precision, disk):
     They go through the FP64 integrator in both modes (in FP32 mode through
     its separate band queue), and each is held to the oracle: classes agree
     (outside a disk-edge zone widened by the band bound), end azimuths and
-    exit directions within 1e-8 + b 1e-10 / |b - b_c| (FP32 mode: exit
-    directions are mapped in FP32, so within 1e-4 plus that), disk radii
-    likewise, colours outside the checker-edge zone."""
+    exit directions within 1e-8 + b D / |b - b_c| (D = 1e-10; FP32 mode, whose
+    band runs at rtol_band 1e-9: D = 1.1e-9, and exit directions are mapped in
+    FP32, so within 1e-4 plus that), disk radii likewise, colours outside the
+    checker-edge zone."""
     f = inputs.Frame(inputs.Camera(30.0, 75.0, 20.0, 21.0, 512, 512), inputs.scene_in_m(1.0, disk))
     rgba, out = gpu_render(bh, f, bh.FP64 if precision == "fp64" else bh.FP32)
     r_rgba, r_rays = ref.render(ref_camera(ref, f.camera), ref_scene(ref, f.scene))

@@ -44,7 +44,7 @@ def test_band_ray_error_beyond_its_bound_fails(band_frame):
     f, rgba, r = band_frame
     d = np.abs(r.b - P.B_CRIT)
     k = int(np.nonzero((d > 1e-2) & (d < 0.05) & (r.cls == 0))[0][0])
-    lim = 1e-8 + r.b[k] * P.BAND_DRIFT / d[k]
+    lim = 1e-8 + r.b[k] * P.BAND_DRIFT["fp64"] / d[k]
     for scale, ok in ((0.5, True), (2.0, False)):
         g = _as_gpu(r)
         g["phi_end"][k] += scale * lim
