@@ -273,10 +273,11 @@ bh::DevTol dev_tol(const bh_options* o, const bh_scene* sc) {
     t.max_steps = o->max_steps;
     // Lazy refill: a wavefront starts new rays once this many lanes are idle
     // (or its queue is dry).  Several steps' worth of finished rays: FP32
-    // rays take ~11 step evaluations, FP64 rays ~60.  Measured on the 4K
-    // orbit: 20 and 6 took ~5% less integrator time than 1, and 28 with the
-    // FP32 batches' 512-ray chunks 2% less again (single renders measured the
-    // same at 20 to 28).
+    // rays took ~11 step evaluations (7.5 with the per-ray tolerance), FP64
+    // rays ~60.  Measured on the 4K orbit: 20 and 6 took ~5% less integrator
+    // time than 1, and 28 with the FP32 batches' 512-ray chunks 2% less again
+    // (single renders measured the same at 20 to 28; at 7.5 steps per ray,
+    // 20 to 36 within 1%).
     t.refill32 = o->refill_fp32 > 0 ? o->refill_fp32 : 28;
     t.refill64 = o->refill_fp64 > 0 ? o->refill_fp64 : 6;
     return t;
@@ -572,8 +573,9 @@ bh_status bh_default_options(bh_options* o) {
     o->rtol_band = 1e-9;
     o->band_halfwidth = 0.05;
     o->h0 = 1e-2;
-    // The FP32 path starts near the step its tolerance allows in the far
-    // field (rtol 1e-6: ~0.2 rad) instead of ramping up from 1e-2.
+    // The FP32 path starts near the step its base tolerance allows in the far
+    // field (rtol 1e-6: ~0.2 rad) instead of ramping up from 1e-2; a ray whose
+    // tolerance grows by f starts at 0.2 f^(1/5).
     o->h0_fp32 = 0.2;
     o->hmax = 1.0;
     o->max_phi = 8.0 * kPi;

@@ -548,7 +548,7 @@ __device__ __forceinline__ void dp45(const G& g_of, T u, T w, T g1, T h, T& un, 
 // (clamped to 5).
 //
 // Safety s: 0.9 for FP64 rays, as the oracle; 0.8 for FP32 rays.  At the
-// FP32 path's tolerances (rtol 1e-6 .. 1e-5) the elementary controller at 0.9
+// FP32 path's tolerances (rtol 1e-6 .. 2e-5) the elementary controller at 0.9
 // keeps proposing steps just too long while the error constant grows towards
 // periapsis (rejected steps had err 1.0-1.5), and about a fifth of all step
 // evaluations were rejections; at 0.8 a ray takes ~15% fewer evaluations with
