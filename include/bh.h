@@ -164,7 +164,7 @@ typedef struct {
 } bh_ray_out;
 
 /* Fills defaults: FP64, rtol 1e-10, atol 0 (-> rtol/r_sky), rtol_fp32 1e-6,
- * rtol_fp32_growth 20, rtol_band 1e-9, band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps
+ * rtol_fp32_growth 50, rtol_band 1e-9, band 0.05, h0 1e-2, h0_fp32 0.2, hmax 1, max_phi 8 pi, max_steps
  * 1e6, analytic capture on, auto launch shape, refill thresholds and batch groups.
  * Returns BH_ERR_ARG for NULL. */
 bh_status bh_default_options(bh_options* opt);

@@ -34,7 +34,7 @@ def test_defaults():
     o = api.options()
     assert o.precision == api.FP64 and o.rtol == 1e-10 and o.atol == 0.0
     assert o.rtol_fp32 == 1e-6 and o.band_halfwidth == 0.05 and o.max_steps == 1000000
-    assert o.rtol_fp32_growth == 20.0 and o.rtol_band == 1e-9
+    assert o.rtol_fp32_growth == 50.0 and o.rtol_band == 1e-9
     assert o.h0 == 1e-2 and o.h0_fp32 == 0.2
     assert abs(o.max_phi - 8 * 3.141592653589793) < 1e-12 and o.analytic_capture == 1
 

@@ -13,15 +13,14 @@ the rays next to the critical band keep it):
   - the first step h0 = 0.2 rad is within 1% of the cheapest of 0.01 .. 0.5;
   - at (0.8, 0.2) the largest exit-azimuth error is below half the 1e-4 rad
     target, and no class differs from the reference.
-With the tolerance growing with |b - b_c| (the library's default growth 20):
-  - a third fewer step evaluations per ray, the largest exit and disk-radius
+With the tolerance growing with |b - b_c| (the library's default growth 50):
+  - 39% fewer step evaluations per ray, the largest exit and disk-radius
     errors unchanged (they come from rays next to the band), class
-    differences only in the disk-edge zone, and 0.8 still the cheapest
-    safety factor.
+    differences only in the disk-edge zone, and 0.8 cheaper than 0.7 and 0.9.
 The GPU's own split (bh_last_stats, reported by the benchmark as
 "controller") on the full orbit is 10.38 accepted, 0.143 rejected and 0.512
-Newton steps per FP32 ray at growth 1, and 6.20, 0.424 and 0.709 at growth
-20; the model gives the same to the second decimal.
+Newton steps per FP32 ray at growth 1, and 5.59, 0.41 and 0.733 at growth
+50; the model gives the same to the second decimal.
 """
 import json
 import math
@@ -104,14 +103,14 @@ def test_safety_factor_and_first_step(model):
 
 
 def test_tolerance_growth(model):
-    base, grown, g07, g09 = model((0.8, 0.2, 1e-6, 1), (0.8, 0.2, 1e-6, 20),
-                                  (0.7, 0.2, 1e-6, 20), (0.9, 0.2, 1e-6, 20))
+    base, grown, g07, g09 = model((0.8, 0.2, 1e-6, 1), (0.8, 0.2, 1e-6, 50),
+                                  (0.7, 0.2, 1e-6, 50), (0.9, 0.2, 1e-6, 50))
     for r in (base, grown, g07, g09):
         print(json.dumps(r))
-    assert evals(grown) < 0.72 * evals(base)
+    assert evals(grown) < 0.65 * evals(base)
     assert grown["max_phi_err"] <= 1.05 * base["max_phi_err"] < 5e-5
     assert grown["max_r_rel"] <= 1.05 * base["max_r_rel"] < 5e-5
     assert grown["class_diff_outside_edge_zone"] == 0
     assert evals(grown) < evals(g07) and evals(grown) < evals(g09)
     # the split the GPU's instrumented integrator measures on the full orbit
-    assert abs(grown["accepted"] - 6.20) < 0.1 and abs(grown["newton"] - 0.709) < 0.02
+    assert abs(grown["accepted"] - 5.59) < 0.1 and abs(grown["newton"] - 0.733) < 0.02
