@@ -273,7 +273,7 @@ bh::DevTol dev_tol(const bh_options* o, const bh_scene* sc) {
     t.max_steps = o->max_steps;
     // Lazy refill: a wavefront starts new rays once this many lanes are idle
     // (or its queue is dry).  Several steps' worth of finished rays: FP32
-    // rays took ~11 step evaluations (7.5 with the per-ray tolerance), FP64
+    // rays took ~11 step evaluations (6.8 with the per-ray tolerance), FP64
     // rays ~60.  Measured on the 4K orbit: 20 and 6 took ~5% less integrator
     // time than 1, and 28 with the FP32 batches' 512-ray chunks 2% less again
     // (single renders measured the same at 20 to 28; at 7.5 steps per ray,
