@@ -119,6 +119,24 @@ def test_fp32_tolerance_growth(bh, ref, growth):
         assert steps < 0.85 * base
 
 
+def test_band_tolerance_applies_to_fp32_mode_only(bh):
+    """rtol_band sets the FP64 integrator's tolerance for the critical band of
+    FP32 mode: FP64 renders are bit-identical whatever its value, while FP32
+    renders change their band rays (and only them)."""
+    f = inputs.Frame(inputs.Camera(30.0, 75.0, 20.0, 21.0, 256, 256), inputs.scene_in_m(1.0, (6.0, 20.0)))
+    a64, o64 = gpu_render(bh, f, bh.FP64)
+    b64, p64 = gpu_render(bh, f, bh.FP64, rtol_band=1e-4)
+    np.testing.assert_array_equal(a64, b64)
+    np.testing.assert_array_equal(o64["phi_end"], p64["phi_end"])
+    _, o32 = gpu_render(bh, f, bh.FP32)
+    _, p32 = gpu_render(bh, f, bh.FP32, rtol_band=1e-6)
+    band = o32["path"] == bh.PATH_FP64
+    assert band.sum() > 1000
+    np.testing.assert_array_equal(o32["phi_end"][~band], p32["phi_end"][~band])
+    assert np.any(o32["phi_end"][band] != p32["phi_end"][band])
+    assert o32["steps"][band].mean() > p32["steps"][band].mean()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("disk", [None, (6.0, 20.0)])
 def test_band_rays_match_oracle(bh, ref, precision, disk):
