@@ -114,7 +114,9 @@ typedef struct {
                                 (single renders and traces: 3/4 of the resident
                                 blocks; batches: all resident blocks)               */
     int    chunk;            /* rays taken from the queue per wavefront grab; 0 = auto
-                                (512 for FP32 batches, 256 otherwise)                */
+                                (512 for FP32 batches; FP32 single renders: at least
+                                256, about four grabs per wavefront of the grid, 384
+                                for a 4K frame; 256 otherwise)                      */
     int    samples_side;     /* bh_render: n x n rays per pixel at the stratified
                                 sub-pixel centres, averaged (box filter); 0 or 1 =
                                 one ray through the pixel centre; at most 16        */

@@ -308,12 +308,24 @@ bh::Out dev_out(const bh_ray_out* o) {
     return d;
 }
 
-// Queue chunk: 256 rays per grab for single renders and FP64 batches, 512 for
-// FP32 batches (their one drain at the end of many requests gains less from
-// small chunks than the grabs cost: the 16-frame 4K orbit integrates 2% faster
-// at 512, with refill 28).
-int auto_chunk(const bh_options* o, bool batch = false) {
-    return o->chunk > 0 ? o->chunk : (batch && o->precision == BH_FP32 ? 512 : 256);
+// Queue chunk: 512 rays per grab for FP32 batches (their one drain at the end
+// of many requests gains less from small chunks than the grabs cost: the
+// 16-frame 4K orbit integrates 2% faster at 512, with refill 28), 256 for FP64
+// renders and batches.  FP32 single renders of n rays take at most about four
+// grabs per wavefront of their grid (3/4 of 8 resident blocks per CU, or
+// grid_blocks): the smallest multiple of 64 rays, at least 256, that does.
+// At 6.8 step evaluations per ray the grabs of 256-ray chunks cost a 4K frame
+// (5.3 grabs per wavefront) 11% of its integration against 384 rays (3.5),
+// while frames of 2560x1440 and smaller (2.4 grabs or fewer) integrate
+// fastest at 256 and 4-14% slower at 320-512.
+int auto_chunk(const bh_options* o, bool batch = false, int64_t n = 0, int cus = 0) {
+    if (o->chunk > 0) return o->chunk;
+    if (batch) return o->precision == BH_FP32 ? 512 : 256;
+    if (o->precision != BH_FP32 || cus <= 0 || n <= 0) return 256;
+    const int64_t waves = (o->grid_blocks > 0 ? (int64_t)o->grid_blocks : (int64_t)cus * 6) * 4;
+    int64_t c = (n + 4 * waves - 1) / (4 * waves);
+    c = (c + 63) / 64 * 64;
+    return (int)std::min<int64_t>(std::max<int64_t>(c, 256), 1024);
 }
 
 bh_status check_camera(const bh_camera* cam, const bh_scene* scene) {
@@ -438,7 +450,8 @@ bh_status run_on(const bh::Work& ws_w, int cus, const bh::Source& src, bool expl
             ? bh::launch_integrate_paper(src.n, explicit_u0, u0_uniform, sc, tol, opt->fixed_eps, w,
                                          cus, stream)
             : bh::launch_integrate(src.n, explicit_u0, u0_uniform, sc, tol, opt->precision, w,
-                                   cus, opt->grid_blocks, auto_chunk(opt), stats, stream);
+                                   cus, opt->grid_blocks, auto_chunk(opt, false, src.n, cus), stats,
+                                   stream);
     timing_end(t, stream);
     if (e != hipSuccess) return hip_fail(e, "integrate");
     t = timed ? timing_begin(2, stream) : -1;
