@@ -263,6 +263,19 @@ def test_schedule_invariance(bh, precision):
             np.testing.assert_array_equal(out[k], base[k], err_msg=f"{kw} {k}")
 
 
+def test_schedule_invariance_at_4k(bh):
+    """A 4K FP32 render takes its queue chunk from its size (384 rays); the
+    pixels and per-ray records equal those of 256- and 512-ray chunks bit for
+    bit."""
+    f = inputs.orbit_4k()[0]
+    base_rgba, base = gpu_render(bh, f, bh.FP32)
+    for c in (256, 512):
+        rgba, out = gpu_render(bh, f, bh.FP32, chunk=c)
+        np.testing.assert_array_equal(rgba, base_rgba, err_msg=f"chunk {c}")
+        for k in ("cls", "phi_end", "r_hit", "steps", "path"):
+            np.testing.assert_array_equal(out[k], base[k], err_msg=f"chunk {c} {k}")
+
+
 def test_step_caps(bh, ref):
     """max_steps and max_phi caps give UNRESOLVED, as in the oracle."""
     f = inputs.plain_64()
